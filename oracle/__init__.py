@@ -1,0 +1,454 @@
+"""FP64 CPU oracle for listmode SPDHG (LM-SPDHG).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline of the benchmark are the only code allowed to import this package.
+It shares no code with the HIP library (``paper_2201_05497_amd``) and never
+imports it; the library never imports this.  Everything is plain, slow,
+float64 and single-threaded, written to be checked against the paper by eye.
+
+The projector pair lives in ``lm_oracle.c`` (compiled with gcc on first
+use); this module holds the algorithm: event counts, subsets, step sizes,
+the dual proxes, the finite-difference operator K, LM-SPDHG (Algorithm 2),
+sinogram SPDHG on a dense system matrix (Algorithm 1) and the cost (Eq. 1).
+
+Readings of the paper taken here, where it is silent or ambiguous:
+
+* event count mu_e: the number of events in the list whose bin (unordered
+  crystal pair, TOF bin with the sign flipped when the pair is swapped) is
+  the bin of e (footnote to Algorithm 2);
+* subsets: event e (0-based chronological index) belongs to subset e mod n
+  (text after Algorithm 2);
+* the subset sequence is an input (random choices are drawn outside);
+* the dual prox of line "y+ <- prox" uses 4 S_e mu_e under the square root
+  (Eq. proxD with d_{i_e} = mu_e; Appendix A gives the same term);
+* z initialisation uses "+": z = P^T 1 + P^LM^T((y-1)/mu) + K^T w, the only
+  sign for which z equals P^T of the sinogram dual built from Eq. (yinit)
+  (the printed "-" contradicts the sentence that follows the algorithm);
+* K = forward differences with zero (Neumann) boundary, no voxel-size
+  scaling; ||K|| is its exact largest singular value;
+* T = min over the subset step sizes and the prior step size:
+  T_j = rho / (2 gamma max(g_j, ||K||)) with p_k = 1/(2n), p_prior = 1/2;
+  S_e = gamma rho / (P^LM 1)_e, and 0 where (P^LM 1)_e = 0.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lm_oracle.c")
+_LIB = os.path.join(_HERE, "liblm_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile lm_oracle.c into liblm_oracle.so with gcc (plain -O2, IEEE)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("det", ctypes.POINTER(ctypes.c_float)),
+                ("n_cry", ctypes.c_int32), ("n_ring", ctypes.c_int32),
+                ("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3),
+                ("n_tof", ctypes.c_int32), ("tof_bin", ctypes.c_double),
+                ("tof_fwhm", ctypes.c_double), ("tof_nsig", ctypes.c_double),
+                ("tof_on", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        sp = ctypes.POINTER(ctypes.c_int16)
+        gp = ctypes.POINTER(_Geom)
+        lib.orc_fwd.argtypes = [gp, dp, sp, ctypes.c_int64, dp]
+        lib.orc_back.argtypes = [gp, dp, sp, ctypes.c_int64, dp]
+        lib.orc_sens.argtypes = [gp, dp]
+        lib.orc_sens_pairs.argtypes = [gp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, dp]
+        lib.orc_count_samples.argtypes = [gp, sp, ctypes.c_int64]
+        lib.orc_count_samples.restype = ctypes.c_int64
+        lib.orc_tof_weight.argtypes = [gp, ctypes.c_int, ctypes.c_double]
+        lib.orc_tof_weight.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+class Geometry:
+    """Scanner table + image grid + TOF parameters, as the C oracle sees them.
+
+    ``det`` is the float32 crystal table; ``n`` = (nx, ny, nz); ``h`` the voxel
+    size in mm; TOF: ``n_tof`` bins of width ``tof_bin``, Gaussian FWHM
+    ``tof_fwhm``, truncated at ``tof_nsig`` sigma; ``tof_on`` False gives the
+    non-TOF projector.
+    """
+
+    def __init__(self, det, n_cry, n_ring, n, h, n_tof, tof_bin, tof_fwhm,
+                 tof_nsig=3.0, tof_on=True):
+        self.det = np.ascontiguousarray(det, dtype=np.float32)
+        assert self.det.shape == (n_cry * n_ring, 3)
+        self.n_cry, self.n_ring = int(n_cry), int(n_ring)
+        self.n = tuple(int(v) for v in n)
+        self.h = tuple(float(v) for v in h)
+        self.n_tof, self.tof_bin, self.tof_fwhm = int(n_tof), float(tof_bin), float(tof_fwhm)
+        self.tof_nsig, self.tof_on = float(tof_nsig), bool(tof_on)
+        self._c = _Geom(self.det.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                        self.n_cry, self.n_ring, (ctypes.c_int32 * 3)(*self.n),
+                        (ctypes.c_double * 3)(*self.h), self.n_tof, self.tof_bin,
+                        self.tof_fwhm, self.tof_nsig, int(self.tof_on))
+
+    @classmethod
+    def from_problem(cls, p, tof_on: Optional[bool] = None) -> "Geometry":
+        sc, img, tof = p.scanner, p.image, p.tof
+        return cls(p.det, sc.n_cry, sc.n_ring, img.n, img.h, tof.n_tof, tof.bin, tof.fwhm,
+                   tof.nsigma, tof.on if tof_on is None else tof_on)
+
+    def with_tof(self, on: bool) -> "Geometry":
+        return Geometry(self.det, self.n_cry, self.n_ring, self.n, self.h, self.n_tof,
+                        self.tof_bin, self.tof_fwhm, self.tof_nsig, on)
+
+    @property
+    def shape(self):
+        """Image array shape, C-order [z][y][x]."""
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def sigma(self) -> float:
+        return self.tof_fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+
+
+def _ev(events) -> np.ndarray:
+    ev = np.ascontiguousarray(events, dtype=np.int16)
+    assert ev.ndim == 2 and ev.shape[1] == 5
+    return ev
+
+
+# --------------------------------------------------------------------------
+# operators (C): P^LM, its adjoint, sensitivity
+
+
+def fwd(geom: Geometry, x: np.ndarray, events) -> np.ndarray:
+    """(P^LM x)_e for every event (Eq. lmop), float64."""
+    lib = _load()
+    ev = _ev(events)
+    xd = np.ascontiguousarray(x, dtype=np.float64).reshape(geom.shape)
+    out = np.zeros(len(ev), dtype=np.float64)
+    lib.orc_fwd(ctypes.byref(geom._c), xd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), len(ev),
+                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def back(geom: Geometry, v: np.ndarray, events, img: Optional[np.ndarray] = None) -> np.ndarray:
+    """img + (P^LM)^T v (the adjoint of ``fwd``), float64."""
+    lib = _load()
+    ev = _ev(events)
+    vd = np.ascontiguousarray(v, dtype=np.float64)
+    assert vd.shape == (len(ev),)
+    out = np.zeros(geom.shape, dtype=np.float64) if img is None else np.array(img, dtype=np.float64)
+    lib.orc_back(ctypes.byref(geom._c), vd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), len(ev),
+                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def sens(geom: Geometry) -> np.ndarray:
+    """g = P^T 1 over all unordered crystal pairs and all TOF bins."""
+    lib = _load()
+    out = np.zeros(geom.shape, dtype=np.float64)
+    lib.orc_sens(ctypes.byref(geom._c), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def sens_pairs(geom: Geometry, pairs: np.ndarray) -> np.ndarray:
+    """P^T 1 over the given crystal-id pairs (int32 [M, 2]) and all TOF bins."""
+    lib = _load()
+    pr = np.ascontiguousarray(pairs, dtype=np.int32)
+    out = np.zeros(geom.shape, dtype=np.float64)
+    lib.orc_sens_pairs(ctypes.byref(geom._c), pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                       len(pr), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def count_samples(geom: Geometry, events) -> int:
+    """Number of Joseph samples (plane x event with non-zero TOF weight)."""
+    ev = _ev(events)
+    return int(_load().orc_count_samples(ctypes.byref(geom._c),
+                                         ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), len(ev)))
+
+
+def tof_weight(geom: Geometry, k: int, t: float) -> float:
+    return float(_load().orc_tof_weight(ctypes.byref(geom._c), int(k), float(t)))
+
+
+def dense_matrix(geom: Geometry, events) -> np.ndarray:
+    """Rows of P for the given events, built by projecting every basis image."""
+    ev = _ev(events)
+    nvox = int(np.prod(geom.n))
+    P = np.zeros((len(ev), nvox))
+    for v in range(nvox):
+        b = np.zeros(nvox)
+        b[v] = 1.0
+        P[:, v] = fwd(geom, b, ev)
+    return P
+
+
+# --------------------------------------------------------------------------
+# event bookkeeping (Algorithm 2, lines 2 and 6)
+
+
+def bin_keys(events, n_cry: int) -> np.ndarray:
+    """Canonical bin of each event: (id1, id2, k) with id1 <= id2, where the
+    two crystals are swapped and k negated when id1 > id2."""
+    ev = np.asarray(events, dtype=np.int64)
+    id1 = ev[:, 0] + n_cry * ev[:, 1]
+    id2 = ev[:, 2] + n_cry * ev[:, 3]
+    k = ev[:, 4]
+    sw = id1 > id2
+    a = np.where(sw, id2, id1)
+    b = np.where(sw, id1, id2)
+    kk = np.where(sw, -k, k)
+    return np.stack([a, b, kk], axis=1)
+
+
+def event_counts(events, n_cry: int) -> np.ndarray:
+    """mu_e = number of events in the list with the same bin as e."""
+    keys = bin_keys(events, n_cry)
+    _u, inv, cnt = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    return cnt[np.asarray(inv).reshape(-1)].astype(np.int64)
+
+
+def subset_ids(n_events: int, n_subsets: int) -> np.ndarray:
+    """Subset of each event: every n-th event goes to the same sublist."""
+    return np.arange(n_events, dtype=np.int64) % n_subsets
+
+
+# --------------------------------------------------------------------------
+# prior: K = forward differences, R = mixed L2-L1 norm (Section 3, TV prior)
+
+
+def grad(x: np.ndarray) -> np.ndarray:
+    """K x: forward differences along x, y, z (array axes 2, 1, 0), zero in
+    the last layer of each axis.  Returns [3][nz][ny][nx]."""
+    out = np.zeros((3,) + x.shape)
+    for comp, ax in enumerate((2, 1, 0)):
+        sl_hi = [slice(None)] * 3
+        sl_lo = [slice(None)] * 3
+        sl_hi[ax] = slice(1, None)
+        sl_lo[ax] = slice(None, -1)
+        out[comp][tuple(sl_lo)] = x[tuple(sl_hi)] - x[tuple(sl_lo)]
+    return out
+
+
+def grad_adjoint(q: np.ndarray) -> np.ndarray:
+    """K^T q, the exact adjoint of ``grad``."""
+    out = np.zeros(q.shape[1:])
+    for comp, ax in enumerate((2, 1, 0)):
+        sl_hi = [slice(None)] * 3
+        sl_lo = [slice(None)] * 3
+        sl_hi[ax] = slice(1, None)
+        sl_lo[ax] = slice(None, -1)
+        qc = q[comp]
+        out[tuple(sl_hi)] += qc[tuple(sl_lo)]
+        out[tuple(sl_lo)] -= qc[tuple(sl_lo)]
+    return out
+
+
+def grad_norm(shape_zyx: Sequence[int]) -> float:
+    """Largest singular value of K: the forward-difference matrix of length N
+    with a zero last row has singular values 2 sin(pi j / (2N)), j < N, so
+    ||K||^2 = sum over axes of 4 sin^2(pi (N-1) / (2N))."""
+    return float(np.sqrt(sum(4.0 * np.sin(np.pi * (N - 1) / (2.0 * N)) ** 2 for N in shape_zyx)))
+
+
+def prox_tv_dual(v: np.ndarray, beta: float) -> np.ndarray:
+    """beta * prox_{R*}(v / beta) for R = ||.||_{2,1}: the projection of v onto
+    the pointwise Euclidean ball of radius beta (v has components first)."""
+    nrm = np.sqrt((v ** 2).sum(axis=0))
+    return v / np.maximum(1.0, nrm / beta)[None]
+
+
+def tv(x: np.ndarray) -> float:
+    return float(np.sqrt((grad(x) ** 2).sum(axis=0)).sum())
+
+
+# --------------------------------------------------------------------------
+# data term
+
+
+def prox_poisson_dual(a: np.ndarray, S: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """prox of S D*(.; d) at a, pointwise (Eq. proxD)."""
+    return 0.5 * (a + 1.0 - np.sqrt((a - 1.0) ** 2 + 4.0 * S * d))
+
+
+def poisson_dual_conj(y: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """D*(y; d) (the conjugate of the Poisson negative log-likelihood)."""
+    y = np.asarray(y, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    out = np.full(np.broadcast(y, d).shape, np.inf)
+    pos = (d > 0) & (y < 1)
+    out = np.where(pos, -d + d * np.log(np.where(pos, d, 1.0) / np.where(pos, 1.0 - y, 1.0)), out)
+    out = np.where((d == 0) & (y <= 1), 0.0, out)
+    return out
+
+
+def cost(geom: Geometry, x: np.ndarray, events, s: np.ndarray, g: np.ndarray, beta: float) -> float:
+    """Listmode form of Eq. (1) without the constant sum of s over all bins:
+    <g, x> - sum_e log((P^LM x)_e + s_e) + beta ||K x||_{2,1}."""
+    q = fwd(geom, x, events) + s
+    return float((g * x).sum() - np.log(q).sum() + beta * tv(x))
+
+
+# --------------------------------------------------------------------------
+# LM-SPDHG (Algorithm 2)
+
+
+@dataclasses.dataclass
+class LMState:
+    x: np.ndarray
+    z: np.ndarray
+    zbar: np.ndarray
+    w: np.ndarray
+    y: np.ndarray
+    u: int = 0
+
+
+@dataclasses.dataclass
+class LMSetup:
+    mu: np.ndarray
+    subsets: list
+    S: np.ndarray
+    S_prior: float
+    T: np.ndarray
+    g: np.ndarray
+    knorm: float
+
+
+def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
+             rho: float, knorm: Optional[float] = None) -> LMSetup:
+    """Event counts, subsets and step sizes (Algorithm 2 lines 2-3, 6;
+    Eq. lm_stepsizes)."""
+    ev = _ev(events)
+    mu = event_counts(ev, geom.n_cry)
+    sub = subset_ids(len(ev), n_subsets)
+    subsets = [np.nonzero(sub == i)[0] for i in range(n_subsets)]
+    P1 = fwd(geom, np.ones(geom.shape), ev)
+    S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
+    kn = grad_norm(geom.shape) if (knorm is None or knorm <= 0) else float(knorm)
+    T = rho / (2.0 * gamma * np.maximum(g, kn))
+    return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn)
+
+
+def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarray) -> LMState:
+    """y = 1 - mu / (P^LM x + s) (line 4); w = 0; z = zbar = g + P^LM^T((y-1)/mu)
+    + K^T w (line 5, with the sign reading described in the module doc)."""
+    ev = _ev(events)
+    x = np.array(x0, dtype=np.float64).reshape(geom.shape)
+    y = 1.0 - setup.mu / (fwd(geom, x, ev) + s)
+    w = np.zeros((3,) + geom.shape)
+    z = setup.g + back(geom, (y - 1.0) / setup.mu, ev) + grad_adjoint(w)
+    return LMState(x=x, z=z, zbar=z.copy(), w=w, y=y, u=0)
+
+
+def lm_update(geom: Geometry, events, s: np.ndarray, setup: LMSetup, st: LMState,
+              i: int, n_subsets: int, beta: float) -> LMState:
+    """One update of Algorithm 2 (lines 8-20) with the subset choice i given."""
+    ev = _ev(events)
+    st.x = np.maximum(0.0, st.x - setup.T * st.zbar)
+    if i < n_subsets:
+        e = setup.subsets[i]
+        q = fwd(geom, st.x, ev[e]) + s[e]
+        a = st.y[e] + setup.S[e] * q
+        yp = prox_poisson_dual(a, setup.S[e], setup.mu[e])
+        dz = back(geom, (yp - st.y[e]) / setup.mu[e], ev[e])
+        st.y[e] = yp
+        p = 1.0 / (2.0 * n_subsets)
+    else:
+        v = st.w + setup.S_prior * grad(st.x)
+        wp = prox_tv_dual(v, beta)
+        dz = grad_adjoint(wp - st.w)
+        st.w = wp
+        p = 0.5
+    st.z = st.z + dz
+    st.zbar = st.z + dz / p
+    st.u += 1
+    return st
+
+
+def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarray,
+             n_subsets: int, seq: Sequence[int], gamma: float, rho: float, beta: float,
+             knorm: Optional[float] = None, state: Optional[LMState] = None,
+             setup: Optional[LMSetup] = None,
+             callback: Optional[Callable[[LMState, LMSetup], None]] = None):
+    """Run the updates listed in ``seq`` (each entry a subset index, or
+    n_subsets for the prior) and return (x, state, setup).  x is the image of
+    the last x-update (the value Algorithm 2 returns)."""
+    s = np.asarray(s, dtype=np.float64)
+    if setup is None:
+        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm)
+    if state is None:
+        state = lm_init(geom, events, s, setup, x0)
+    for i in seq:
+        lm_update(geom, events, s, setup, state, int(i), n_subsets, beta)
+        if callback is not None:
+            callback(state, setup)
+    return state.x, state, setup
+
+
+# --------------------------------------------------------------------------
+# sinogram SPDHG (Algorithm 1) on a dense system matrix, with the y
+# initialisation of Eq. (yinit); used only to check LM-SPDHG on tiny problems
+
+
+def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins_of_subset,
+               seq, gamma: float, rho: float, beta: float, shape_zyx,
+               T: Optional[np.ndarray] = None, knorm: Optional[float] = None):
+    """P: [m, nvox] rows of the TOF sinogram operator; d: counts per bin;
+    bins_of_subset: list of bin-index arrays; T: primal step, by default the
+    preconditioned rule of Algorithm 1, T = min_k T_k with
+    T_k = rho p_k / (gamma P_k^T 1) and T_prior = rho p_prior / (gamma ||K||),
+    p_k = 1/(2n), p_prior = 1/2; returns x after the updates."""
+    n = len(bins_of_subset)
+    kn = grad_norm(shape_zyx) if (knorm is None or knorm <= 0) else float(knorm)
+    P1 = P.sum(axis=1)
+    S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
+    S_prior = gamma * rho / kn
+    if T is None:
+        Tk = [rho * (1.0 / (2 * n)) / (gamma * P[b].sum(axis=0)) for b in bins_of_subset]
+        T = np.minimum(np.min(np.stack(Tk), axis=0), rho * 0.5 / (gamma * kn))
+    x = np.array(x0, dtype=np.float64).reshape(-1)
+    y = 1.0 - d / (P @ x + s)
+    w = np.zeros((3,) + tuple(shape_zyx))
+    z = P.T @ y + grad_adjoint(w).reshape(-1)
+    zbar = z.copy()
+    Tf = np.asarray(T, dtype=np.float64).reshape(-1)
+    for i in seq:
+        x = np.maximum(0.0, x - Tf * zbar)
+        if i < n:
+            b = bins_of_subset[i]
+            a = y[b] + S[b] * (P[b] @ x + s[b])
+            yp = prox_poisson_dual(a, S[b], d[b])
+            dz = P[b].T @ (yp - y[b])
+            y[b] = yp
+            p = 1.0 / (2.0 * n)
+        else:
+            v = w + S_prior * grad(x.reshape(shape_zyx))
+            wp = prox_tv_dual(v, beta)
+            dz = grad_adjoint(wp - w).reshape(-1)
+            w = wp
+            p = 0.5
+        z = z + dz
+        zbar = z + dz / p
+    return x.reshape(shape_zyx)
