@@ -1,0 +1,212 @@
+"""Benchmark of the LM-SPDHG hot path on one MI355X.
+
+Workload: the 3D TOF listmode problem (cylinder of 672 crystals x 96 rings,
+R = 380 mm, 200x200x96 image of 2.6 mm voxels, 33 TOF bins of 24 mm, FWHM
+60 mm), 1e7 Monte-Carlo prompts with 30 % smooth contamination, 224
+subsets, TV beta = 0.03.  One step = one LM-SPDHG epoch (448 updates: data
+subsets and prior updates drawn with p = 1/(2n) and 1/2), continuing the
+reconstruction from the previous step.  Inputs are resident in HBM before
+the timed region; the plan (event counts, subsets, step sizes, the
+sensitivity image from lm_sens) is built before it.
+
+Prints one JSON line: value = events forward- and back-projected per second
+over the timed epochs, plus the per-kernel roofline of the dominant kernel
+(HIP events around every launch of the update loop, recorded by the
+library on its stream) and the FP64 oracle timed on a bounded sample of the
+same workload on the host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+N_SUB = 224
+BETA = 0.03
+RHO = 0.999
+SEQ_SEED = 2001
+DATA_SEED = 1001
+N_EVENTS = 10_000_000
+
+# algorithmic bytes per unit of each kernel class:
+#   image kernels: bytes per voxel read + written once;
+#   data update: bytes per event of the per-event lists (record, S, mu, c r/w)
+BYTES_PER_VOXEL = {"primal": 16, "dual_image": 28, "tv_dual": 28, "tv_adjoint": 44}
+BYTES_PER_EVENT = 16 + 4 + 4 + 4 + 4
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, g, n_sample_subsets: int = 3):
+    """The FP64 oracle on a bounded sample of the workload: the events of a
+    few data subsets (the sample problem) are initialised untimed, then as
+    many data updates and prior updates are timed and scaled to one epoch."""
+    import oracle
+    G = oracle.Geometry.from_problem(p)
+    n = N_SUB
+    ev_idx = np.concatenate([np.arange(i, len(p.events), n) for i in range(n_sample_subsets)])
+    ev = p.events[ev_idx]
+    s = p.s[ev_idx].astype(np.float64)
+    gamma = float(np.float32(3.0 / float(p.x0.max())))
+    # the sample problem has n_sample_subsets subsets: its subset i is the
+    # workload's subset i (interleaved split)
+    su = oracle.lm_setup(G, ev, n_sample_subsets, g, gamma, RHO)
+    st = oracle.lm_init(G, ev, s, su, p.x0)
+    t0 = time.perf_counter()
+    n_ev = 0
+    for i in range(n_sample_subsets):
+        oracle.lm_update(G, ev, s, su, st, i, n_sample_subsets, BETA)
+        n_ev += len(su.subsets[i])
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(n_sample_subsets):
+        oracle.lm_update(G, ev, s, su, st, n_sample_subsets, n_sample_subsets, BETA)
+    t_prior = time.perf_counter() - t0
+    # one epoch: N events in (expected) n data updates plus n prior updates
+    t_epoch = t_data * (len(p.events) / n_ev) + t_prior * (n / n_sample_subsets)
+    return {
+        "value": len(p.events) / t_epoch,
+        "unit": "events/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{n_sample_subsets} of {n} data subsets ({n_ev} events) and {n_sample_subsets} prior "
+                   f"updates on the 200x200x96 image, timed ({t_data:.1f} s + {t_prior:.1f} s) and scaled "
+                   f"to one epoch ({t_epoch:.0f} s/epoch)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--events", type=int, default=N_EVENTS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path is a design "
+                                   "(see DESIGN.md) and is not built", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    import lmsynth
+    import paper_2201_05497_amd as P
+
+    t0 = time.perf_counter()
+    p = lmsynth.simulate_3d(lmsynth.config_3d(), n_prompts=args.events, seed=DATA_SEED)
+    log(f"generated {len(p.events)} events in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    G = P.Geometry.from_problem(p, device=dev)
+    ev = G.events(p.events)
+    s = torch.as_tensor(p.s, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = P.lm_sens(G)
+    torch.cuda.synchronize()
+    t_sens = time.perf_counter() - t0
+    log(f"lm_sens over {G.n_cry * G.n_ring * (G.n_cry * G.n_ring - 1) // 2} crystal pairs: {t_sens:.2f} s")
+    gamma = float(np.float32(3.0 / float(p.x0.max())))
+    t0 = time.perf_counter()
+    plan = P.Plan(G, ev, s, N_SUB, gamma, RHO, BETA, g=g)
+    t_plan = time.perf_counter() - t0
+    x = torch.as_tensor(p.x0, device=dev).clone()
+    plan.init(x)
+    torch.cuda.synchronize()
+    log(f"plan + init: {t_plan:.2f} s")
+    perm, off = plan.layout()
+    sizes = (off[1:] - off[:-1]).cpu().numpy()
+
+    u = 0
+    seqs = []
+    for _ in range(args.warmup + args.steps):
+        seqs.append(lmsynth.subset_sequence(SEQ_SEED, u, 2 * N_SUB, N_SUB))
+        u += 2 * N_SUB
+    for k in range(args.warmup):
+        plan.epoch(x, seqs[k])
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        plan.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        plan.epoch(x, seqs[k])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    timing = plan.get_timing() if not args.no_timing else None
+    plan.timing(False)
+
+    n_proj = sum(int(sizes[seq[seq < N_SUB]].sum()) for seq in seqs[args.warmup:])
+    value = n_proj / t_total
+    ms_per_step = 1e3 * t_total / args.steps
+    log(f"{args.steps} epochs in {t_total:.3f} s: {ms_per_step:.2f} ms/epoch, {value:.3e} events/s")
+
+    roof = None
+    kernels = None
+    if timing:
+        nvox = G.nvox
+        kernels = {}
+        for k, (ms, cnt) in timing.items():
+            if cnt == 0:
+                continue
+            kernels[k] = {"ms_total": ms, "launches": cnt, "us_avg": 1e3 * ms / cnt}
+        dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+        d = kernels[dom]
+        if dom == "data_update":
+            n_ev = n_proj
+            bytes_per_launch = BYTES_PER_EVENT * n_ev / d["launches"]
+        else:
+            bytes_per_launch = BYTES_PER_VOXEL[dom] * nvox
+        achieved = bytes_per_launch / (d["us_avg"] * 1e-6) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(bytes_per_launch), "us_per_launch": round(d["us_avg"], 2)}
+        for k, v in kernels.items():
+            if k in BYTES_PER_VOXEL:
+                v["GBs"] = round(BYTES_PER_VOXEL[k] * nvox / (v["us_avg"] * 1e-6) / 1e9, 1)
+        kernels["data_update"]["events_per_s"] = round(n_proj / (kernels["data_update"]["ms_total"] * 1e-3), 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        # the oracle's cost does not depend on the values of g; it gets its own
+        # input (no GPU output is ever fed to the oracle)
+        cpu = cpu_baseline(p, np.ones(G.shape))
+        log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
+
+    out = {
+        "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
+        "value": round(value, 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "s_per_epoch": round(ms_per_step / 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3d_672x96_200x200x96: 1e7 TOF events (30% contamination), 224 subsets, "
+                               "TV beta 0.03, one LM-SPDHG epoch per step",
+                   "events": len(p.events), "subsets": N_SUB, "image": list(G.shape)},
+        "roofline": roof,
+        "kernels": kernels,
+        "setup_s": {"lm_sens": round(t_sens, 3), "plan_create": round(t_plan, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.destroy()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

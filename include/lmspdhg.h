@@ -1,0 +1,219 @@
+/*
+ * lmspdhg.h -- C ABI of the MI355X (gfx950) listmode SPDHG library.
+ *
+ * The library solves the Poisson problem of the paper's Eq. (1),
+ *     argmin_{x >= 0}  sum_i (Px+s)_i - d_i log (Px+s)_i  +  beta ||Kx||_{2,1},
+ * event by event (listmode), with the stochastic primal-dual algorithm
+ * LM-SPDHG (Algorithm 2).  P is a time-of-flight Joseph projector, K the
+ * forward-difference gradient (Section 3, the TV prior).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work on it unless marked "synchronous".
+ *  - Every call returns LM_OK (0) or a negative error code; a thread-local
+ *    message is available from lm_last_error().  No C++ exception crosses
+ *    the ABI.  On an error return nothing has been enqueued.
+ *  - Images are float32, C-order [z][y][x] (x fastest), voxel (i, j, k)
+ *    centred at ((i-(nx-1)/2) hx, (j-(ny-1)/2) hy, (k-(nz-1)/2) hz) mm.
+ *  - An event is int16[5] = (c1, r1, c2, r2, k): crystal c1 of ring r1,
+ *    crystal c2 of ring r2, signed TOF bin k with |k| <= (n_tof-1)/2 (the
+ *    paper's 10-byte event, Table 1).  The crystal id is c + n_cry * r.
+ *    Events with an out-of-range id or TOF bin contribute nothing to any
+ *    projection (their forward value is 0); lm_validate_events reports them
+ *    and lm_plan_create rejects them.
+ *
+ * The projector (the paper specifies only "Joseph" and a Gaussian TOF
+ * kernel; Section 2, "Listmode SPDHG", and Section 3):
+ *  - the LOR of an event runs from p1 = det[id1] to p2 = det[id2];
+ *  - Joseph: dominant axis a = argmax_b |fl32(p2_b - p1_b)| (ties to the
+ *    lower axis x < y < z); one sample per image plane perpendicular to a
+ *    with the LOR parameter lam in [0, 1]; bilinear interpolation over the
+ *    two other axes (corners outside the image count as zero); each sample
+ *    weighted by the plane length h_a |p2-p1| / |p2_a - p1_a|;
+ *  - TOF: t = signed distance of the sample from the LOR centre, positive
+ *    towards p2; bin k is centred at k*tof_bin with width tof_bin; the
+ *    kernel is a Gaussian of FWHM tof_fwhm truncated at tof_nsigma sigmas,
+ *    renormalised to unit mass, integrated over the bin.  tof_on = 0 gives
+ *    the non-TOF projector (weight 1).
+ */
+#ifndef LMSPDHG_H
+#define LMSPDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LM_OK = 0,
+  LM_EINVAL = -1, /* bad shape, size or parameter */
+  LM_ERANGE = -2, /* crystal, ring or TOF index out of range */
+  LM_ENOMEM = -3, /* device allocation failed */
+  LM_EHIP = -4,   /* a HIP runtime call failed (message has the HIP text) */
+  LM_ESTATE = -5  /* plan used before lm_spdhg_init, or inconsistent state */
+};
+
+/* Scanner, image grid and TOF model.  `det` is a DEVICE pointer to
+ * float[n_cry * n_ring][3] crystal centres in mm (id = c + n_cry * r); it
+ * must stay valid while calls that use this geometry run.  The scalars are
+ * double: the per-event set-up of the projector runs in double precision,
+ * and a float voxel size (2.6f != 2.6) would shift the grid by ~1e-5 mm at
+ * the image edge. */
+typedef struct lm_geom {
+  const float *det;
+  int32_t n_cry, n_ring;
+  int32_t n[3];      /* image size nx, ny, nz (each 1..512) */
+  double h[3];       /* voxel size in mm */
+  int32_t n_tof;     /* odd number of TOF bins (>= 1) */
+  double tof_bin;    /* TOF bin width, mm */
+  double tof_fwhm;   /* Gaussian FWHM, mm */
+  double tof_nsigma; /* truncation in sigmas (> 0) */
+  int32_t tof_on;    /* 0: non-TOF projector */
+} lm_geom;
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char *lm_last_error(void);
+
+/* ---------------------------------------------------------------- projector */
+
+/* Listmode forward projection (Eq. lmop): out[e] = (P^LM x)_e for the n
+ * events ev[n][5] in the caller's order.  x: image; out: float[n]. */
+int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out,
+           void *stream);
+
+/* Listmode back projection, the adjoint of lm_fwd: img += (P^LM)^T v.  It
+ * ACCUMULATES (FP32 atomics, so the summation order is not fixed); the
+ * caller zeroes img.  v: float[n]. */
+int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img,
+            void *stream);
+
+/* Sensitivity image g += P^T 1 over every unordered crystal pair and every
+ * TOF bin (the back projection of a sinogram of ones that Algorithm 2's
+ * initialisation and the step sizes T need; Section 2, after Eq.
+ * lm_stepsizes).  Accumulates into g; the caller zeroes it. */
+int lm_sens(const lm_geom *G, float *g, void *stream);
+
+/* Synchronous: count events whose crystal, ring or TOF index is out of
+ * range.  *n_bad (host) receives the count. */
+int lm_validate_events(const lm_geom *G, const int16_t *ev, int64_t n, int64_t *n_bad,
+                       void *stream);
+
+/* ---------------------------------------------------------------- prior */
+
+/* gx = K x: forward differences along x, y, z (Section 3, TV prior), zero
+ * in the last layer of each axis; gx is float[3][nz][ny][nx] (component 0 =
+ * x).  n = {nx, ny, nz} (host array). */
+int tv_grad(const int32_t n[3], const float *x, float *gx, void *stream);
+
+/* out = div w = -K^T w (the negative adjoint of tv_grad); w is
+ * float[3][nz][ny][nx]. */
+int tv_div(const int32_t n[3], const float *w, float *out, void *stream);
+
+/* ---------------------------------------------------------------- LM-SPDHG */
+
+typedef struct lm_plan lm_plan;
+
+/* Device bytes a plan for n_ev events and n_sub subsets will allocate,
+ * including the temporary memory of lm_plan_create; host output *bytes.
+ * Used to admit reconstructions against an HBM budget. */
+int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes);
+
+/* Synchronous.  Builds a plan: copies and validates the events (LM_ERANGE
+ * on any out-of-range index, nothing allocated), computes the event counts
+ * mu_e (Algorithm 2 and its footnote: the number of events in the list in
+ * the same sinogram bin, i.e. the same unordered crystal pair and TOF bin
+ * with the sign of k flipped when the pair is swapped), splits the list
+ * into n_sub interleaved subsets (event e goes to subset e mod n_sub, the
+ * text after Algorithm 2), and the step sizes of Eq. lm_stepsizes with
+ * p_k = 1/(2 n_sub) and p_prior = 1/2 (Section 3):
+ *   S_e = gamma rho / (P^LM 1)_e  (0 where the LOR misses the image),
+ *   S_prior = gamma rho / knorm,
+ *   T_j = rho / (2 gamma max(g_j, knorm)).
+ * ev: int16[n][5]; s: float[n] contamination per event (> 0); g: the
+ * sensitivity image or NULL (then lm_sens is run); knorm <= 0 selects the
+ * exact norm of K, sqrt(sum_a 4 sin^2(pi (N_a-1) / (2 N_a))).  The plan
+ * keeps a copy of G (det must stay valid) and owns all its device memory
+ * until lm_plan_destroy.  Work runs on `stream`; the call returns after it
+ * finished. */
+int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int32_t n_sub,
+                   const float *g, double gamma, double rho, double beta, double knorm, void *stream,
+                   lm_plan **out);
+
+/* Initialisation (Algorithm 2): y_e = 1 - mu_e / ((P^LM x0)_e + s_e),
+ * w = 0, z = zbar = g + (P^LM)^T((y - 1)/mu) + K^T w.  (The printed
+ * initialisation of z has "-" before the back projection; "+" is the sign under which z is the
+ * back projection of the sinogram dual of Eq. yinit, as the text after the
+ * algorithm states.)  Resets the update counter to 0. */
+int lm_spdhg_init(lm_plan *p, const float *x0, void *stream);
+
+/* Runs n_updates updates of Algorithm 2.  seq_host (host) lists
+ * the random choices: entry u is a data subset 0..n_sub-1 or n_sub for the
+ * prior update; the caller draws them with p_k = 1/(2 n_sub), p_prior = 1/2.
+ * x (in/out, float image) enters as the x returned by the previous call (x0
+ * after init) and leaves as the x of the last update's primal step (the
+ * value Algorithm 2 returns).  Calls on one plan must be ordered (one
+ * stream).  LM_EINVAL if an entry of seq is out of range (nothing run). */
+int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq_host, int32_t n_updates, void *stream);
+
+/* Number of events, subsets and the image size of a plan (host outputs,
+ * any may be NULL). */
+int lm_plan_info(const lm_plan *p, int64_t *n_ev, int32_t *n_sub, int64_t *nvox);
+
+/* Read back per-event lists in the caller's event order: y (dual variable,
+ * float[n], rounded from the stored complement 1 - y, see below), mu (event
+ * counts, int32[n]), subset (subset index, int32[n]), p1 (P^LM 1, float[n]);
+ * any output may be NULL.  Enqueued on stream. */
+int lm_plan_get_lists(const lm_plan *p, float *y, int32_t *mu, int32_t *subset, float *p1,
+                      void *stream);
+
+/* Internal processing order: perm[j] = caller index of the j-th stored
+ * event (int32[n]); offsets[i] = first stored position of subset i
+ * (int32[n_sub + 1]).  Either may be NULL. */
+int lm_plan_get_layout(const lm_plan *p, int32_t *perm, int32_t *offsets, void *stream);
+
+/* Device images of the plan state: sensitivity g and primal step T
+ * (float[nvox]); either may be NULL. */
+int lm_plan_get_images(const lm_plan *p, float *g, float *T, void *stream);
+
+/* Checkpoint.  The state is x (held by the caller), and z, zbar,
+ * w (float[3][nvox]), c = 1 - y (float[n], caller event order) plus the
+ * update counter.  The plan stores the dual as its complement c, which
+ * stays accurate where y tends to 1; checkpoints carry c so that a resumed
+ * run continues from exactly the stored state.  get copies the state out
+ * into caller buffers (any may be NULL); set copies it in and marks the
+ * plan initialised.  *u (host) is the update counter. */
+int lm_plan_get_state(const lm_plan *p, float *z, float *zbar, float *w, float *c, int64_t *u,
+                      void *stream);
+int lm_plan_set_state(lm_plan *p, const float *z, const float *zbar, const float *w,
+                      const float *c, int64_t u, void *stream);
+
+/* Kernel classes of lm_spdhg_epoch, for lm_plan_get_timing. */
+enum {
+  LM_K_PRIMAL = 0,      /* primal step at the start of a call */
+  LM_K_DATA = 1,        /* fused forward / dual prox / back projection of a subset */
+  LM_K_DUAL_IMAGE = 2,  /* z, zbar (and fused primal) after a data update */
+  LM_K_TV_DUAL = 3,     /* w_new = proj(w + S K x) */
+  LM_K_TV_ADJOINT = 4,  /* K^T(w_new - w), z, zbar (and fused primal) */
+  LM_K_COUNT = 5
+};
+
+/* Per-kernel timing of lm_spdhg_epoch: while enabled, every launch of the
+ * plan's update loop is bracketed by a pair of HIP events on the stream it
+ * runs on.  lm_plan_get_timing (synchronous) adds the elapsed times of all
+ * recorded launches to ms[LM_K_COUNT] and their number to
+ * launches[LM_K_COUNT] (host arrays, accumulated since the last reset =
+ * lm_plan_timing(p, 1)). */
+int lm_plan_timing(lm_plan *p, int enable);
+int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
+
+/* Frees the plan's device memory (synchronises its last stream first). */
+int lm_plan_destroy(lm_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMSPDHG_H */

@@ -340,10 +340,10 @@ def _sample_3d_points(rng, n):
 
 def _trues(rng, n, sc: Scanner, tof: TOF, dim: int):
     det64 = det_table(sc).astype(np.float64)
-    ev = np.empty((0, 5), dtype=np.int64)
+    blocks, have, acc = [], 0, 0.5
     zmax = sc.axial_half
-    while len(ev) < n:
-        m = int(1.3 * (n - len(ev))) + 1024
+    while have < n:
+        m = min(int(1.1 * (n - have) / acc) + 1024, 4_000_000)
         if dim == 2:
             P2 = _sample_2d_points(rng, m)
             P = np.concatenate([P2, np.zeros((m, 1))], axis=1)
@@ -366,8 +366,10 @@ def _trues(rng, n, sc: Scanner, tof: TOF, dim: int):
         k = _tof_bins(P, det64, c1, r1, c2, r2, sc, tof, rng)
         ok &= np.abs(k) <= tof.kmax
         blk = np.stack([c1, r1, c2, r2, k], axis=1)[ok]
-        ev = np.concatenate([ev, blk])
-    return ev[:n]
+        acc = max(len(blk) / m, 0.02)
+        blocks.append(blk)
+        have += len(blk)
+    return np.concatenate(blocks)[:n]
 
 
 def _random_pairs(rng, m, sc: Scanner):
@@ -452,17 +454,54 @@ def simulate_2d(p: Problem, n_prompts: int = 100_000, contam_frac: float = 0.2,
     return _finish(rng, trues, contam, s[:n_t], s[n_t:], p, seed)
 
 
+CHUNK = 500_000  # events per independently seeded generation chunk
+
+
+def _chunk(task):
+    kind, count, seed_seq, sc, tof = task
+    rng = np.random.default_rng(seed_seq)
+    if kind == "t":
+        return _trues(rng, count, sc, tof, 3)
+    return _contamination(rng, count, sc, tof, smooth=True)
+
+
+def _chunked(kind: str, n: int, seed_seq, sc: Scanner, tof: TOF):
+    counts = [CHUNK] * (n // CHUNK) + ([n % CHUNK] if n % CHUNK else [])
+    return [(kind, c, ss, sc, tof) for c, ss in zip(counts, seed_seq.spawn(len(counts)))]
+
+
 def simulate_3d(p: Problem, n_prompts: int = 10_000_000, contam_frac: float = 0.3,
-                seed: int = 1001) -> Problem:
+                seed: int = 1001, workers: int | None = None) -> Problem:
     """Prompts of the 3D ellipsoid phantom: trues by Monte Carlo (isotropic
     directions accepted when both ends hit the crystal cylinder), plus
     contamination whose per-bin expectation is a smooth Gaussian profile in
-    the LOR's distance from the axis; s_e is that expectation."""
-    rng = np.random.default_rng(seed)
+    the LOR's distance from the axis; s_e is that expectation.  Generated in
+    chunks of CHUNK events with seeds spawned from `seed`, so the result does
+    not depend on the number of worker processes."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    root = np.random.SeedSequence(seed)
+    s_main, s_t, s_c = root.spawn(3)
+    rng = np.random.default_rng(s_main)
     n_c = int(round(contam_frac * n_prompts))
     n_t = n_prompts - n_c
-    trues = _trues(rng, n_t, p.scanner, p.tof, 3)
-    contam = _contamination(rng, n_c, p.scanner, p.tof, smooth=True)
+    tasks = _chunked("t", n_t, s_t, p.scanner, p.tof) + _chunked("c", n_c, s_c, p.scanner, p.tof)
+    if workers is None:
+        workers = min(len(tasks), os.cpu_count() or 1, 16)
+    res = None
+    if workers > 1 and len(tasks) > 1:
+        try:
+            with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+                res = list(ex.map(_chunk, tasks))
+        except (RuntimeError, OSError):
+            # e.g. a calling script without a __main__ guard: generate serially
+            res = None
+    if res is None:
+        res = [_chunk(t) for t in tasks]
+    nt_chunks = len(_chunked("t", n_t, s_t, p.scanner, p.tof))
+    trues = np.concatenate(res[:nt_chunks]) if nt_chunks else np.empty((0, 5), np.int64)
+    contam = np.concatenate(res[nt_chunks:]) if len(res) > nt_chunks else np.empty((0, 5), np.int64)
     s0 = _contamination_level(rng, p.scanner, p.tof, n_c, smooth=True)
     det64 = det_table(p.scanner).astype(np.float64)
     ev_all = np.concatenate([trues, contam])

@@ -19,7 +19,7 @@ Readings of the paper taken here, where it is silent or ambiguous:
 * subsets: event e (0-based chronological index) belongs to subset e mod n
   (text after Algorithm 2);
 * the subset sequence is an input (random choices are drawn outside);
-* the dual prox of line "y+ <- prox" uses 4 S_e mu_e under the square root
+* the dual prox of the data branch uses 4 S_e mu_e under the square root
   (Eq. proxD with d_{i_e} = mu_e; Appendix A gives the same term);
 * z initialisation uses "+": z = P^T 1 + P^LM^T((y-1)/mu) + K^T w, the only
   sign for which z equals P^T of the sinogram dual built from Eq. (yinit)
@@ -206,7 +206,7 @@ def dense_matrix(geom: Geometry, events) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# event bookkeeping (Algorithm 2, lines 2 and 6)
+# event bookkeeping (Algorithm 2: event counts and the split into sublists)
 
 
 def bin_keys(events, n_cry: int) -> np.ndarray:
@@ -226,7 +226,10 @@ def bin_keys(events, n_cry: int) -> np.ndarray:
 def event_counts(events, n_cry: int) -> np.ndarray:
     """mu_e = number of events in the list with the same bin as e."""
     keys = bin_keys(events, n_cry)
-    _u, inv, cnt = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    # one integer per bin: (id1, id2, k) packed into 20 + 20 + 20 bits
+    assert keys[:, :2].max(initial=0) < (1 << 20) and np.abs(keys[:, 2]).max(initial=0) < (1 << 19)
+    flat = (keys[:, 0] << 40) | (keys[:, 1] << 20) | (keys[:, 2] + (1 << 19))
+    _u, inv, cnt = np.unique(flat, return_inverse=True, return_counts=True)
     return cnt[np.asarray(inv).reshape(-1)].astype(np.int64)
 
 
@@ -338,7 +341,7 @@ class LMSetup:
 
 def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
              rho: float, knorm: Optional[float] = None) -> LMSetup:
-    """Event counts, subsets and step sizes (Algorithm 2 lines 2-3, 6;
+    """Event counts, subsets and step sizes (Algorithm 2, preprocessing;
     Eq. lm_stepsizes)."""
     ev = _ev(events)
     mu = event_counts(ev, geom.n_cry)
@@ -352,8 +355,9 @@ def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float
 
 
 def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarray) -> LMState:
-    """y = 1 - mu / (P^LM x + s) (line 4); w = 0; z = zbar = g + P^LM^T((y-1)/mu)
-    + K^T w (line 5, with the sign reading described in the module doc)."""
+    """Initialisation of Algorithm 2: y = 1 - mu / (P^LM x + s); w = 0;
+    z = zbar = g + P^LM^T((y-1)/mu) + K^T w (with the sign reading described
+    in the module doc)."""
     ev = _ev(events)
     x = np.array(x0, dtype=np.float64).reshape(geom.shape)
     y = 1.0 - setup.mu / (fwd(geom, x, ev) + s)
@@ -364,7 +368,8 @@ def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarra
 
 def lm_update(geom: Geometry, events, s: np.ndarray, setup: LMSetup, st: LMState,
               i: int, n_subsets: int, beta: float) -> LMState:
-    """One update of Algorithm 2 (lines 8-20) with the subset choice i given."""
+    """One update of Algorithm 2 (primal step, one dual branch, z and zbar)
+    with the subset choice i given."""
     ev = _ev(events)
     st.x = np.maximum(0.0, st.x - setup.T * st.zbar)
     if i < n_subsets:

@@ -1,0 +1,78 @@
+// Host-side helpers shared by the translation units of the library: error
+// reporting through the C ABI, conversion of lm_geom into the kernel form,
+// and the launch shape of the projector kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "lm_device.hpp"
+#include "lmspdhg.h"
+
+namespace lmh {
+
+// thread-local message of the last error (defined in lm_plan.hip)
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define LM_TRY_HIP(expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      lmh::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return LM_EHIP;                                                                     \
+    }                                                                                     \
+  } while (0)
+
+#define LM_REQUIRE(cond, code, ...)   \
+  do {                                \
+    if (!(cond)) {                    \
+      lmh::set_error(__VA_ARGS__);    \
+      return (code);                  \
+    }                                 \
+  } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int kMaxDim = 512;
+
+// Checks lm_geom and converts it; returns LM_OK or LM_EINVAL.
+int make_geom(const lm_geom *G, lmk::GeomDev *out);
+
+// Largest number of planes a single event can visit (bound used to size
+// the per-lane sample cache of the projector kernels).
+int max_planes(const lmk::GeomDev &g, int mode);
+
+// Lanes per event and cached samples per lane for a plane bound.
+struct Launch {
+  int lpe;    // lanes per event: 16, 32 or 64
+  int jmax;   // samples per lane: 1, 2, 3, 4, 6 or 8
+};
+Launch pick_launch(int planes);
+
+// Voxel count with overflow check.
+inline long long nvox_of(const int n[3]) { return (long long)n[0] * n[1] * n[2]; }
+
+}  // namespace lmh
+
+// Kernel launchers defined in lm_project.hip, used by the plan code.
+namespace lmk {
+int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n, float *out,
+               hipStream_t st);
+int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img,
+                hipStream_t st);
+int launch_sens(const GeomDev &g, float *img, hipStream_t st);
+// Plan-internal event records: int4 {id1, id2, k, s bits}.
+int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
+                   hipStream_t st);
+int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long n, float *img,
+                    hipStream_t st);
+// Fused data update of one subset (Algorithm 2, data branch); cdual holds
+// the complement 1 - y of the dual variable.
+int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const float *S,
+                       const float *mu, float *cdual, float *dz, long long n, hipStream_t st);
+}  // namespace lmk

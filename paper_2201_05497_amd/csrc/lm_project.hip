@@ -1,0 +1,401 @@
+// Listmode TOF Joseph projector kernels for gfx950 and their C ABI entry
+// points: lm_fwd, lm_back, lm_sens, lm_validate_events, plus the fused
+// subset update of LM-SPDHG used by the plan code.
+//
+// The forward operator is the paper's listmode operator (Eq. lmop): one
+// row of the TOF system matrix per event.  The fused update evaluates, for
+// every event of a subset, the forward value, the dual prox (Eq. proxD with
+// d = mu_e) and back-projects the scaled dual increment (the data-subset
+// branch of Algorithm 2) in a single pass, so the samples of the forward pass are reused
+// from registers by the back projection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lm_device.hpp"
+#include "lm_host.hpp"
+
+using namespace lmk;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Event sources: the caller's int16[5] records, or the plan's int4 records.
+struct CallerEvents {
+  const int16_t *ev;
+  CallerEvents offset(long long o) const { return CallerEvents{ev + 5 * o}; }
+  __device__ __forceinline__ bool get(const GeomDev &g, long long e, int &id1, int &id2, int &k) const {
+    return decode_event(g, ev + 5 * e, id1, id2, k);
+  }
+};
+struct PlanEvents {
+  const int4 *rec;
+  PlanEvents offset(long long o) const { return PlanEvents{rec + o}; }
+  __device__ __forceinline__ bool get(const GeomDev &, long long e, int &id1, int &id2, int &k) const {
+    const int4 r = rec[e];
+    id1 = r.x;
+    id2 = r.y;
+    k = r.z;
+    return true;
+  }
+};
+
+template <int LPE, class Src>
+__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, const float *__restrict__ x, Src src,
+                                                long long n, float *__restrict__ out) {
+  const int lane = threadIdx.x % LPE;
+  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  if (e >= n) return;
+  int id1 = 0, id2 = 0, k = 0;
+  float acc = 0.0f, L = 0.0f;
+  if (src.get(g, e, id1, id2, k)) {
+    const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
+    L = r.L;
+    for (int j = lane; j < r.nplanes; j += LPE) {
+      const Sample s = sample_at(g, r, j, g.tof_on);
+      acc = fmaf(s.w, gather(x, r, s), acc);
+    }
+  }
+  acc = group_sum<LPE>(acc);
+  if (lane == 0) out[e] = L * acc;
+}
+
+template <int LPE, class Src>
+__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restrict__ v, Src src,
+                                                 long long n, float *img) {
+  const int lane = threadIdx.x % LPE;
+  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  if (e >= n) return;
+  const float ve = v[e];
+  if (ve == 0.0f) return;
+  int id1, id2, k;
+  if (!src.get(g, e, id1, id2, k)) return;
+  const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
+  const float c = r.L * ve;
+  for (int j = lane; j < r.nplanes; j += LPE) {
+    const Sample s = sample_at(g, r, j, g.tof_on);
+    if (s.w != 0.0f) scatter(img, r, s, c * s.w);
+  }
+}
+
+// Sensitivity: every unordered pair (id1 < id2) of crystals, weight summed
+// over all TOF bins.  Pair index p in [p0, p0 + np) of the row-major upper
+// triangle.
+template <int LPE>
+__global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, long long p0, long long np, float *img) {
+  const int lane = threadIdx.x % LPE;
+  const long long q = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  if (q >= np) return;
+  const long long p = p0 + q;
+  const long long nd = g.n_det;
+  // row i holds pairs (i, i+1..nd-1); first index of row i is i*nd - i(i+1)/2
+  const double b = 2.0 * nd - 1.0;
+  long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+  auto first = [&](long long r) { return r * nd - r * (r + 1) / 2; };
+  if (i < 0) i = 0;
+  while (i > 0 && first(i) > p) --i;
+  while (i + 1 < nd && first(i + 1) <= p) ++i;
+  const long long jdx = i + 1 + (p - first(i));
+  const Ray r = setup_ray(g, (int)i, (int)jdx, 0, W_SUM, 1 << 20);
+  for (int j = lane; j < r.nplanes; j += LPE) {
+    const Sample s = sample_at(g, r, j, g.tof_on);
+    if (s.w != 0.0f) scatter(img, r, s, r.L * s.w);
+  }
+}
+
+// Fused subset update (the data-subset branch of Algorithm 2) for the events of one
+// subset, stored contiguously in the plan's order:
+//   q = (P x)_e + s_e;  y+ = prox(y_e + S_e q) with d = mu_e;
+//   dz += P^T((y+ - y_e)/mu_e);  y_e = y+.
+// The dual is kept as its complement c = 1 - y (y tends to 1 on LORs with
+// large expected counts, where 1 - y would cancel), and the increment is
+// evaluated in the cancellation-free form
+//   y+ - y = 2 S (q c - mu) / (S q + c + sqrt((S q - c)^2 + 4 S mu)),
+// algebraically identical to Eq. proxD minus y; c+ = c - (y+ - y).
+template <int LPE, int JMAX>
+__global__ __launch_bounds__(kBlock) void k_data_update(GeomDev g, const float *__restrict__ x,
+                                                        const int4 *__restrict__ rec,
+                                                        const float *__restrict__ S,
+                                                        const float *__restrict__ mu,
+                                                        float *__restrict__ cdual, float *dz, long long n) {
+  const int lane = threadIdx.x % LPE;
+  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  if (e >= n) return;
+  const int4 rc = rec[e];
+  const float Se = S[e];
+  if (Se == 0.0f) return;  // LOR misses the image: the prox leaves y unchanged
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, JMAX * LPE);
+  Sample cache[JMAX];
+  float acc = 0.0f;
+#pragma unroll
+  for (int jj = 0; jj < JMAX; ++jj) {
+    const int j = lane + jj * LPE;
+    if (j < r.nplanes) {
+      cache[jj] = sample_at(g, r, j, g.tof_on);
+      acc = fmaf(cache[jj].w, gather(x, r, cache[jj]), acc);
+    } else {
+      cache[jj].w = 0.0f;
+    }
+  }
+  acc = group_sum<LPE>(acc);
+  const float q = fmaf(r.L, acc, __int_as_float(rc.w));
+  const float c = cdual[e], me = mu[e];
+  const float sq = Se * q;
+  const float t = sq - c;
+  const float rt = sqrtf(fmaf(t, t, 4.0f * Se * me));
+  const float dy = 2.0f * Se * fmaf(q, c, -me) / (sq + c + rt);
+  if (lane == 0) cdual[e] = c - dy;
+  if (dy == 0.0f) return;
+  const float cf = r.L * (dy / me);
+#pragma unroll
+  for (int jj = 0; jj < JMAX; ++jj) {
+    if (cache[jj].w != 0.0f) scatter(dz, r, cache[jj], cf * cache[jj].w);
+  }
+}
+
+// Counts events with an out-of-range crystal, ring or TOF index.
+__global__ void k_validate(GeomDev g, const int16_t *ev, long long n, unsigned long long *bad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int id1, id2, k;
+  const bool ok = (e >= n) || decode_event(g, ev + 5 * e, id1, id2, k);
+  const unsigned long long m = __ballot(!ok);
+  if ((threadIdx.x % 64) == 0 && m) atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
+template <class F>
+int dispatch_lpe(int lpe, F &&f) {
+  switch (lpe) {
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    default: return f(std::integral_constant<int, 64>{});
+  }
+}
+
+inline unsigned blocks_for(long long n, int lpe) {
+  const long long per = kBlock / lpe;
+  return (unsigned)((n + per - 1) / per);
+}
+
+// A launch covers at most 2^22 blocks (2^30 work-items): the total number
+// of work-items of one dispatch must stay below 2^32.  Larger inputs are
+// processed in consecutive launches on the same stream.
+constexpr long long kMaxBlocks = 1LL << 22;
+inline long long chunk_items(int lpe) { return kMaxBlocks * (kBlock / lpe); }
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// geometry and launch policy
+
+namespace lmh {
+
+int make_geom(const lm_geom *G, lmk::GeomDev *o) {
+  LM_REQUIRE(G != nullptr, LM_EINVAL, "lm_geom is NULL");
+  LM_REQUIRE(G->det != nullptr, LM_EINVAL, "lm_geom.det is NULL");
+  LM_REQUIRE(G->n_cry > 0 && G->n_ring > 0, LM_EINVAL, "n_cry and n_ring must be positive");
+  LM_REQUIRE((long long)G->n_cry * G->n_ring < (1LL << 30), LM_EINVAL, "too many crystals");
+  for (int a = 0; a < 3; ++a) {
+    LM_REQUIRE(G->n[a] >= 1 && G->n[a] <= kMaxDim, LM_EINVAL, "image size n[%d]=%d outside 1..%d", a,
+               G->n[a], kMaxDim);
+    LM_REQUIRE(G->h[a] > 0.0 && std::isfinite(G->h[a]), LM_EINVAL, "voxel size h[%d] must be > 0", a);
+  }
+  LM_REQUIRE(G->n_tof >= 1 && (G->n_tof % 2) == 1 && G->n_tof < 32767, LM_EINVAL,
+             "n_tof must be odd and positive");
+  if (G->tof_on) {
+    LM_REQUIRE(G->tof_bin > 0.0 && G->tof_fwhm > 0.0 && G->tof_nsigma > 0.0, LM_EINVAL,
+               "TOF bin, FWHM and truncation must be positive");
+  }
+  o->det = G->det;
+  o->n_cry = G->n_cry;
+  o->n_ring = G->n_ring;
+  o->n_det = G->n_cry * G->n_ring;
+  for (int a = 0; a < 3; ++a) {
+    o->n[a] = G->n[a];
+    o->h[a] = G->h[a];
+    o->c0[a] = -0.5 * (G->n[a] - 1) * G->h[a];
+  }
+  o->stride[0] = 1;
+  o->stride[1] = G->n[0];
+  o->stride[2] = G->n[0] * G->n[1];
+  o->n_tof = G->n_tof;
+  o->kmax = (G->n_tof - 1) / 2;
+  o->tof_on = G->tof_on ? 1 : 0;
+  const double sigma = G->tof_fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  o->tof_bin = G->tof_bin;
+  o->inv_sr2 = G->tof_on ? 1.0 / (sigma * std::sqrt(2.0)) : 0.0;
+  o->half_win = G->tof_on ? G->tof_nsigma * sigma + 0.5 * G->tof_bin : 0.0;
+  o->vclip = (float)(G->tof_nsigma / std::sqrt(2.0));
+  o->inv_norm = (float)(1.0 / (2.0 * std::erf(G->tof_nsigma / std::sqrt(2.0))));
+  return LM_OK;
+}
+
+int max_planes(const lmk::GeomDev &g, int mode) {
+  const int nmax = std::max(g.n[0], std::max(g.n[1], g.n[2]));
+  if (!g.tof_on || mode == lmk::W_SUM) return nmax;
+  const double hmin = std::min(g.h[0], std::min(g.h[1], g.h[2]));
+  // the LOR advances at least h_a along t per plane; +3 covers the margins
+  const long long b = (long long)std::ceil(2.0 * g.half_win / hmin) + 3;
+  return (int)std::min<long long>(b, nmax);
+}
+
+Launch pick_launch(int planes) {
+  Launch l;
+  l.lpe = planes > 96 ? 64 : 32;
+  int j = (planes + l.lpe - 1) / l.lpe;
+  static const int opts[] = {1, 2, 3, 4, 6, 8};
+  l.jmax = 8;
+  for (int o : opts)
+    if (o >= j) {
+      l.jmax = o;
+      break;
+    }
+  return l;
+}
+
+}  // namespace lmh
+
+// --------------------------------------------------------------------------
+// launchers
+
+namespace lmk {
+
+template <class Src>
+static int fwd_impl(const GeomDev &g, const float *x, Src src, long long n, float *out, hipStream_t st) {
+  if (n == 0) return LM_OK;
+  const int lpe = lmh::pick_launch(lmh::max_planes(g, W_BIN)).lpe;
+  return dispatch_lpe(lpe, [&](auto c) {
+    constexpr int L = decltype(c)::value;
+    for (long long o = 0; o < n; o += chunk_items(L)) {
+      const long long m = std::min(chunk_items(L), n - o);
+      hipLaunchKernelGGL((k_fwd<L, Src>), dim3(blocks_for(m, L)), dim3(kBlock), 0, st, g, x, src.offset(o), m,
+                         out + o);
+      LM_TRY_HIP(hipGetLastError());
+    }
+    return LM_OK;
+  });
+}
+
+template <class Src>
+static int back_impl(const GeomDev &g, const float *v, Src src, long long n, float *img, hipStream_t st) {
+  if (n == 0) return LM_OK;
+  const int lpe = lmh::pick_launch(lmh::max_planes(g, W_BIN)).lpe;
+  return dispatch_lpe(lpe, [&](auto c) {
+    constexpr int L = decltype(c)::value;
+    for (long long o = 0; o < n; o += chunk_items(L)) {
+      const long long m = std::min(chunk_items(L), n - o);
+      hipLaunchKernelGGL((k_back<L, Src>), dim3(blocks_for(m, L)), dim3(kBlock), 0, st, g, v + o, src.offset(o), m,
+                         img);
+      LM_TRY_HIP(hipGetLastError());
+    }
+    return LM_OK;
+  });
+}
+
+int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n, float *out, hipStream_t st) {
+  return fwd_impl(g, x, CallerEvents{ev}, n, out, st);
+}
+int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st) {
+  return back_impl(g, v, CallerEvents{ev}, n, img, st);
+}
+int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out, hipStream_t st) {
+  return fwd_impl(g, x, PlanEvents{rec}, n, out, st);
+}
+int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long n, float *img, hipStream_t st) {
+  return back_impl(g, v, PlanEvents{rec}, n, img, st);
+}
+
+int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
+  const long long nd = g.n_det;
+  const long long npairs = nd * (nd - 1) / 2;
+  constexpr int L = 64;
+  const long long chunk = chunk_items(L);
+  for (long long p0 = 0; p0 < npairs; p0 += chunk) {
+    const long long np = std::min(chunk, npairs - p0);
+    hipLaunchKernelGGL((k_sens<L>), dim3(blocks_for(np, L)), dim3(kBlock), 0, st, g, p0, np, img);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  return LM_OK;
+}
+
+int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const float *S, const float *mu,
+                       float *cdual, float *dz, long long n, hipStream_t st) {
+  if (n == 0) return LM_OK;
+  const lmh::Launch l = lmh::pick_launch(lmh::max_planes(g, W_BIN));
+#define LM_DU(LPE_, J_)                                                                         \
+  if (l.lpe == LPE_ && l.jmax == J_) {                                                          \
+    for (long long o = 0; o < n; o += chunk_items(LPE_)) {                                      \
+      const long long m = std::min(chunk_items(LPE_), n - o);                                   \
+      hipLaunchKernelGGL((k_data_update<LPE_, J_>), dim3(blocks_for(m, LPE_)), dim3(kBlock), 0, st, g, \
+                         x, rec + o, S + o, mu + o, cdual + o, dz, m);                          \
+      LM_TRY_HIP(hipGetLastError());                                                            \
+    }                                                                                           \
+    return LM_OK;                                                                               \
+  }
+  LM_DU(32, 1) LM_DU(32, 2) LM_DU(32, 3)
+  LM_DU(64, 2) LM_DU(64, 3) LM_DU(64, 4) LM_DU(64, 6) LM_DU(64, 8)
+#undef LM_DU
+  lmh::set_error("no update kernel for %d lanes x %d samples", l.lpe, l.jmax);
+  return LM_EINVAL;
+}
+
+}  // namespace lmk
+
+// --------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out, void *stream) {
+  lmh::clear_error();
+  GeomDev g;
+  if (int rc = lmh::make_geom(G, &g)) return rc;
+  LM_REQUIRE(n >= 0, LM_EINVAL, "negative event count");
+  LM_REQUIRE(n == 0 || (x && ev && out), LM_EINVAL, "NULL array");
+  return launch_fwd(g, x, ev, n, out, lmh::as_stream(stream));
+}
+
+int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img, void *stream) {
+  lmh::clear_error();
+  GeomDev g;
+  if (int rc = lmh::make_geom(G, &g)) return rc;
+  LM_REQUIRE(n >= 0, LM_EINVAL, "negative event count");
+  LM_REQUIRE(n == 0 || (v && ev && img), LM_EINVAL, "NULL array");
+  return launch_back(g, v, ev, n, img, lmh::as_stream(stream));
+}
+
+int lm_sens(const lm_geom *G, float *img, void *stream) {
+  lmh::clear_error();
+  GeomDev g;
+  if (int rc = lmh::make_geom(G, &g)) return rc;
+  LM_REQUIRE(img != nullptr, LM_EINVAL, "NULL image");
+  return launch_sens(g, img, lmh::as_stream(stream));
+}
+
+int lm_validate_events(const lm_geom *G, const int16_t *ev, int64_t n, int64_t *n_bad, void *stream) {
+  lmh::clear_error();
+  GeomDev g;
+  if (int rc = lmh::make_geom(G, &g)) return rc;
+  LM_REQUIRE(n >= 0 && n_bad != nullptr, LM_EINVAL, "bad arguments");
+  *n_bad = 0;
+  if (n == 0) return LM_OK;
+  LM_REQUIRE(ev != nullptr, LM_EINVAL, "NULL events");
+  hipStream_t st = lmh::as_stream(stream);
+  unsigned long long *d = nullptr;
+  LM_TRY_HIP(hipMallocAsync((void **)&d, sizeof(unsigned long long), st));
+  hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, ev, (long long)n, d);
+    e = hipGetLastError();
+  }
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFreeAsync(d, st);
+  LM_TRY_HIP(e);
+  *n_bad = (int64_t)h;
+  return LM_OK;
+}
+
+}  // extern "C"
