@@ -193,7 +193,7 @@ int lm_plan_set_state(lm_plan *p, const float *z, const float *zbar, const float
 
 /* Kernel classes of lm_spdhg_epoch, for lm_plan_get_timing. */
 enum {
-  LM_K_PRIMAL = 0,      /* primal step at the start of a call */
+  LM_K_PRIMAL = 0,      /* primal step at the start of a call, layout conversions of x */
   LM_K_DATA = 1,        /* fused forward / dual prox / back projection of a subset */
   LM_K_DUAL_IMAGE = 2,  /* z, zbar (and fused primal) after a data update */
   LM_K_TV_DUAL = 3,     /* w_new = proj(w + S K x) */

@@ -3,9 +3,6 @@
 // One event is handled by a group of LPE lanes (LPE = 16, 32 or 64) of a
 // 64-wide wavefront; the lanes of a group walk the image planes of the
 // event's line of response, lane l taking planes m0 + l, m0 + l + LPE, ...
-// For a LOR whose dominant axis is x, consecutive lanes then read
-// consecutive x addresses, so the gathers of a group are coalesced along the
-// fastest image axis.
 //
 // The per-event set-up (dominant axis, plane range, interpolation and TOF
 // coefficients) is done in double precision, once per event.  The
@@ -14,6 +11,17 @@
 // per event plus F + j*V with j the plane offset inside the event's range,
 // and the TOF argument as A - j*B, so float32 rounding stays at the 1e-6
 // level of a voxel or a TOF sigma.
+//
+// Voxel addresses go through a Layout: images are either row-major
+// ([z][y][x], the caller's layout) or stored in bricks of 4x4x4 voxels (4x4x1
+// for a single slice), 256 bytes each, so that the few planes a ray spends
+// in a brick touch the same cache lines whatever the ray's direction.  The
+// FP32 atomics of the back projection are served per cache line, so the
+// number of lines one atomic instruction touches sets its cost.
+//
+// The functions below except the atomic scatters and group_sum are
+// __host__ __device__ so that the projector can also be exercised by a CPU
+// build.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,15 +29,46 @@
 
 namespace lmk {
 
-// The functions below except scatter and group_sum are __host__ __device__
-// so that the projector can also be exercised by a CPU build.
+// Voxel (i, j, k) -> linear index.  Bricks are 2^sx x 2^sy x 2^sz voxels;
+// nbx, nby bricks per brick row and brick slice.  Row-major is the special
+// case sx = sy = sz = 0 with nbx = nx, nby = ny.
+struct Layout {
+  int nbx, nby, nbz;
+  int sx, sy, sz;    // log2 of the brick size along x, y, z
+};
+
+__host__ __device__ __forceinline__ int vidx(const Layout &L, int i, int j, int k) {
+  const int b = ((k >> L.sz) * L.nby + (j >> L.sy)) * L.nbx + (i >> L.sx);
+  const int mx = (1 << L.sx) - 1, my = (1 << L.sy) - 1, mz = (1 << L.sz) - 1;
+  return (b << (L.sx + L.sy + L.sz)) | ((((k & mz) << L.sy) | (j & my)) << L.sx) | (i & mx);
+}
+
+// Inverse of vidx: position p of the layout -> voxel (i, j, k) (padding
+// positions decode to coordinates beyond the image size).
+__host__ __device__ __forceinline__ void vpos(const Layout &L, long long p, int &i, int &j, int &k) {
+  const int sh = L.sx + L.sy + L.sz;
+  const long long b = p >> sh;
+  const int loc = (int)(p & ((1LL << sh) - 1));
+  const int li = loc & ((1 << L.sx) - 1);
+  const int lj = (loc >> L.sx) & ((1 << L.sy) - 1);
+  const int lk = loc >> (L.sx + L.sy);
+  const long long bi = b % L.nbx, bj = (b / L.nbx) % L.nby, bk = b / ((long long)L.nbx * L.nby);
+  i = (int)(bi << L.sx) | li;
+  j = (int)(bj << L.sy) | lj;
+  k = (int)(bk << L.sz) | lk;
+}
+
+// Elements of an image stored with layout L (the padded brick grid).
+__host__ __device__ __forceinline__ long long layout_size(const Layout &L) {
+  return (long long)L.nbx * L.nby * L.nbz << (L.sx + L.sy + L.sz);
+}
 
 // Geometry in the form the kernels use (built on the host from lm_geom).
 struct GeomDev {
   const float *det;  // [n_det][3]
   int n_cry, n_ring, n_det;
   int n[3];          // nx, ny, nz
-  int stride[3];     // 1, nx, nx*ny
+  Layout lay;        // voxel addressing of the images the kernels see
   double h[3];
   double c0[3];      // coordinate of the centre of voxel 0 along each axis
   int n_tof, kmax;
@@ -45,7 +84,7 @@ struct GeomDev {
 struct Ray {
   int nplanes;       // planes to visit (0: nothing)
   int m0;            // first plane along the dominant axis
-  int sa, s1, s2;    // voxel strides of the dominant axis and the two others
+  int a;             // dominant axis
   int n1, n2;        // image size along the two other axes
   int I1, I2;        // integer parts of the interpolation coordinates at m0
   float F1, V1, F2, V2;  // u_b(m0 + j) = I_b + F_b + j V_b
@@ -72,10 +111,10 @@ __host__ __device__ __forceinline__ int dominant_axis(float dx, float dy, float 
 // Sets up the LOR from crystal id1 to id2 with TOF bin k.  mode W_SUM sets
 // up the weight summed over all TOF bins (the sensitivity image).
 __host__ __device__ __forceinline__ Ray setup_ray(const GeomDev &g, int id1, int id2, int k, int mode,
-                                         int max_planes) {
+                                                  int max_planes) {
   Ray r;
   r.nplanes = 0;
-  r.m0 = r.sa = r.s1 = r.s2 = r.n1 = r.n2 = r.I1 = r.I2 = 0;
+  r.m0 = r.a = r.n1 = r.n2 = r.I1 = r.I2 = 0;
   r.F1 = r.V1 = r.F2 = r.V2 = r.A = r.B = r.D = r.L = 0.0f;
   const float *q1 = g.det + 3 * id1;
   const float *q2 = g.det + 3 * id2;
@@ -163,9 +202,7 @@ __host__ __device__ __forceinline__ Ray setup_ray(const GeomDev &g, int id1, int
   if (np > max_planes) np = max_planes;  // never reached for a valid plan bound
   r.nplanes = np;
   r.m0 = m0;
-  r.sa = sel3(a, g.stride[0], g.stride[1], g.stride[2]);
-  r.s1 = sel3(b1, g.stride[0], g.stride[1], g.stride[2]);
-  r.s2 = sel3(b2, g.stride[0], g.stride[1], g.stride[2]);
+  r.a = a;
   r.n1 = nb1;
   r.n2 = nb2;
   const double u1 = U1 + m0 * V1, u2 = U2 + m0 * V2;
@@ -210,10 +247,10 @@ __host__ __device__ __forceinline__ float tof_weight(float vh, float vl, float v
   return w * inv_norm;
 }
 
-// One sample of a ray: voxel index of the lower corner and the weights.
+// One sample of a ray: plane, lower corner and weights.
 struct Sample {
-  int base;     // index of corner (i1, i2) in plane m (may be out of range)
-  int i1, i2;   // corner indices along the two other axes
+  int m;        // plane along the dominant axis
+  int i1, i2;   // lower corner along the two other axes (may be out of range)
   float f1, f2; // fractional parts
   float w;      // TOF weight (1 without TOF); 0 = no sample
 };
@@ -227,7 +264,7 @@ __host__ __device__ __forceinline__ Sample sample_at(const GeomDev &g, const Ray
   s.f2 = u2 - fl2;
   s.i1 = r.I1 + (int)fl1;
   s.i2 = r.I2 + (int)fl2;
-  s.base = (r.m0 + j) * r.sa + s.i1 * r.s1 + s.i2 * r.s2;
+  s.m = r.m0 + j;
   if (tof_on) {
     const float vh = fmaf(-(float)j, r.B, r.A);
     s.w = tof_weight(vh, vh - r.D, g.vclip, g.inv_norm);
@@ -237,32 +274,82 @@ __host__ __device__ __forceinline__ Sample sample_at(const GeomDev &g, const Ray
   return s;
 }
 
+// Index of voxel (plane m, u1, u2) of a ray with dominant axis a.
+__host__ __device__ __forceinline__ int ray_vidx(const Layout &L, int a, int m, int u1, int u2) {
+  const int i = (a == 0) ? m : u1;
+  const int j = (a == 0) ? u1 : ((a == 1) ? m : u2);
+  const int k = (a == 2) ? m : u2;
+  return vidx(L, i, j, k);
+}
+
+// Corner c (bit 0: +1 along the first other axis, bit 1: along the second)
+// of a sample: its voxel index, or -1 outside the image, and its bilinear
+// weight.
+__host__ __device__ __forceinline__ int corner(const GeomDev &g, const Ray &r, const Sample &s, int c,
+                                               float &wc) {
+  const int u1 = s.i1 + (c & 1), u2 = s.i2 + (c >> 1);
+  wc = ((c & 1) ? s.f1 : 1.0f - s.f1) * ((c & 2) ? s.f2 : 1.0f - s.f2);
+  if ((unsigned)u1 >= (unsigned)r.n1 || (unsigned)u2 >= (unsigned)r.n2) return -1;
+  return ray_vidx(g.lay, r.a, s.m, u1, u2);
+}
+
 // Bilinear gather of a sample (corners outside the image read as zero).
-__host__ __device__ __forceinline__ float gather(const float *__restrict__ img, const Ray &r, const Sample &s) {
-  const bool a0 = (unsigned)s.i1 < (unsigned)r.n1;
-  const bool a1 = (unsigned)(s.i1 + 1) < (unsigned)r.n1;
-  const bool b0 = (unsigned)s.i2 < (unsigned)r.n2;
-  const bool b1 = (unsigned)(s.i2 + 1) < (unsigned)r.n2;
-  float v00 = (a0 && b0) ? img[s.base] : 0.0f;
-  float v10 = (a1 && b0) ? img[s.base + r.s1] : 0.0f;
-  float v01 = (a0 && b1) ? img[s.base + r.s2] : 0.0f;
-  float v11 = (a1 && b1) ? img[s.base + r.s1 + r.s2] : 0.0f;
-  const float lo = fmaf(s.f1, v10 - v00, v00);
-  const float hi = fmaf(s.f1, v11 - v01, v01);
+__host__ __device__ __forceinline__ float gather(const GeomDev &g, const float *__restrict__ img, const Ray &r,
+                                                 const Sample &s) {
+  float v[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float wc;
+    const int ix = corner(g, r, s, c, wc);
+    v[c] = (ix >= 0) ? img[ix] : 0.0f;
+  }
+  const float lo = fmaf(s.f1, v[1] - v[0], v[0]);
+  const float hi = fmaf(s.f1, v[3] - v[2], v[2]);
   return fmaf(s.f2, hi - lo, lo);
 }
 
-// Bilinear scatter-add of c into the four corners.
-__device__ __forceinline__ void scatter(float *img, const Ray &r, const Sample &s, float c) {
-  const bool a0 = (unsigned)s.i1 < (unsigned)r.n1;
-  const bool a1 = (unsigned)(s.i1 + 1) < (unsigned)r.n1;
-  const bool b0 = (unsigned)s.i2 < (unsigned)r.n2;
-  const bool b1 = (unsigned)(s.i2 + 1) < (unsigned)r.n2;
-  const float g1 = 1.0f - s.f1, g2 = 1.0f - s.f2;
-  if (a0 && b0) atomicAdd(img + s.base, c * g1 * g2);
-  if (a1 && b0) atomicAdd(img + s.base + r.s1, c * s.f1 * g2);
-  if (a0 && b1 && s.f2 != 0.0f) atomicAdd(img + s.base + r.s2, c * g1 * s.f2);
-  if (a1 && b1 && s.f2 != 0.0f) atomicAdd(img + s.base + r.s1 + r.s2, c * s.f1 * s.f2);
+// Bilinear scatter-add of c into the four corners (one atomic per corner).
+__device__ __forceinline__ void scatter(const GeomDev &g, float *img, const Ray &r, const Sample &s, float c) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float wc;
+    const int ix = corner(g, r, s, q, wc);
+    if (ix >= 0 && wc != 0.0f) atomicAdd(img + ix, c * wc);
+  }
+}
+
+// Scatter of one sample per lane of a full 64-lane wavefront with the
+// corners interleaved: the four corner contributions of every lane are
+// staged in LDS and issued as four atomic instructions, each covering the 4
+// corners of 16 consecutive planes, which sit in few bricks.  All 64 lanes
+// must call it (lanes without a sample pass c = 0).  sidx / sval point to
+// this wavefront's 256 slots of index and value.
+__device__ __forceinline__ void scatter_interleaved(const GeomDev &g, float *img, const Ray &r, const Sample &s,
+                                                    float c, int lane, int *sidx, float *sval) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float wc;
+    const int ix = corner(g, r, s, q, wc);
+    const bool on = (c != 0.0f) && (ix >= 0) && (wc != 0.0f);
+    sidx[4 * lane + q] = on ? ix : -1;
+    sval[4 * lane + q] = c * wc;
+  }
+  // LDS operations of one wavefront complete in order; the fences keep the
+  // compiler from moving the reads above the writes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // round q takes slots 64 q .. 64 q + 63: the 4 corners of planes
+    // 16 q .. 16 q + 15, consecutive lanes on the corners of one plane
+    const int slot = 64 * q + lane;
+    const int ix = sidx[slot];
+    if (ix >= 0) atomicAdd(img + ix, sval[slot]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Sum over the LPE lanes of a group (all lanes receive the total).
@@ -275,7 +362,7 @@ __device__ __forceinline__ float group_sum(float v) {
 
 // Crystal ids and TOF bin of a caller event int16[5]; false if out of range.
 __host__ __device__ __forceinline__ bool decode_event(const GeomDev &g, const int16_t *ev, int &id1, int &id2,
-                                             int &k) {
+                                                      int &k) {
   const int c1 = ev[0], r1 = ev[1], c2 = ev[2], r2 = ev[3];
   k = ev[4];
   if ((unsigned)c1 >= (unsigned)g.n_cry || (unsigned)c2 >= (unsigned)g.n_cry) return false;

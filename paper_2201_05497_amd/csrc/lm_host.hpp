@@ -57,6 +57,29 @@ Launch pick_launch(int planes);
 // Voxel count with overflow check.
 inline long long nvox_of(const int n[3]) { return (long long)n[0] * n[1] * n[2]; }
 
+// Row-major layout of an n[0] x n[1] x n[2] image (the caller's layout).
+inline lmk::Layout row_major(const int n[3]) {
+  lmk::Layout L;
+  L.nbx = n[0];
+  L.nby = n[1];
+  L.nbz = n[2];
+  L.sx = L.sy = L.sz = 0;
+  return L;
+}
+
+// Brick layout of the plans: 4 x 4 x 4 voxels per brick (4 x 4 x 1 for a
+// single slice), the grid padded up to whole bricks.
+inline lmk::Layout brick_layout(const int n[3]) {
+  lmk::Layout L;
+  L.sx = 2;
+  L.sy = 2;
+  L.sz = n[2] > 1 ? 2 : 0;
+  L.nbx = (n[0] + 3) >> 2;
+  L.nby = (n[1] + 3) >> 2;
+  L.nbz = (n[2] + (1 << L.sz) - 1) >> L.sz;
+  return L;
+}
+
 }  // namespace lmh
 
 // Kernel launchers defined in lm_project.hip, used by the plan code.

@@ -46,29 +46,29 @@ __global__ __launch_bounds__(kBlock) void k_dual_image(float *__restrict__ z, fl
 
 // Prior update, part 1 (the dual prior step of Algorithm 2, R = ||.||_{2,1}):
 //   v = w + S_prior K x;  w_new = v / max(1, |v| / beta)  (pointwise norm).
-// w and w_new hold ncomp components of nv voxels each (ncomp = 2 for a 2D
-// image, whose z-component is identically zero).
+// Images use layout L (ne elements, padding skipped); w and w_new hold ncomp
+// components of ne elements each (ncomp = 2 for a single-slice image, whose
+// z-component is identically zero).
 __global__ __launch_bounds__(kBlock) void k_tv_dual(const float *__restrict__ x, const float *__restrict__ w,
-                                                    float *__restrict__ wn, int nx, int ny, int nz,
-                                                    int ncomp, float Sp, float beta) {
-  const long long nv = (long long)nx * ny * nz;
-  const long long v = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (v >= nv) return;
-  const int i = (int)(v % nx);
-  const int j = (int)((v / nx) % ny);
-  const int k = (int)(v / ((long long)nx * ny));
-  const float xv = x[v];
-  const float gx = (i < nx - 1) ? x[v + 1] - xv : 0.0f;
-  const float gy = (j < ny - 1) ? x[v + nx] - xv : 0.0f;
-  const float gz = (ncomp == 3 && k < nz - 1) ? x[v + (long long)nx * ny] - xv : 0.0f;
-  const float v0 = fmaf(Sp, gx, w[v]);
-  const float v1 = fmaf(Sp, gy, w[nv + v]);
-  const float v2 = (ncomp == 3) ? fmaf(Sp, gz, w[2 * nv + v]) : 0.0f;
+                                                    float *__restrict__ wn, lmk::Layout L, int nx, int ny, int nz,
+                                                    long long ne, int ncomp, float Sp, float beta) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= ne) return;
+  int i, j, k;
+  lmk::vpos(L, p, i, j, k);
+  if (i >= nx || j >= ny || k >= nz) return;
+  const float xv = x[p];
+  const float gx = (i < nx - 1) ? x[lmk::vidx(L, i + 1, j, k)] - xv : 0.0f;
+  const float gy = (j < ny - 1) ? x[lmk::vidx(L, i, j + 1, k)] - xv : 0.0f;
+  const float gz = (ncomp == 3 && k < nz - 1) ? x[lmk::vidx(L, i, j, k + 1)] - xv : 0.0f;
+  const float v0 = fmaf(Sp, gx, w[p]);
+  const float v1 = fmaf(Sp, gy, w[ne + p]);
+  const float v2 = (ncomp == 3) ? fmaf(Sp, gz, w[2 * ne + p]) : 0.0f;
   const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
   const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
-  wn[v] = v0 * sc;
-  wn[nv + v] = v1 * sc;
-  if (ncomp == 3) wn[2 * nv + v] = v2 * sc;
+  wn[p] = v0 * sc;
+  wn[ne + p] = v1 * sc;
+  if (ncomp == 3) wn[2 * ne + p] = v2 * sc;
 }
 
 // Prior update, part 2 (the back-projection through K^T and the z / zbar
@@ -77,31 +77,63 @@ __global__ __launch_bounds__(kBlock) void k_tv_dual(const float *__restrict__ x,
 __global__ __launch_bounds__(kBlock) void k_tv_adjoint(const float *__restrict__ w,
                                                        const float *__restrict__ wn, float *__restrict__ z,
                                                        float *__restrict__ x, const float *__restrict__ T,
-                                                       float *__restrict__ zbar, int nx, int ny, int nz,
-                                                       int ncomp, float inv_p, int fuse) {
+                                                       float *__restrict__ zbar, lmk::Layout L, int nx, int ny,
+                                                       int nz, long long ne, int ncomp, float inv_p, int fuse) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= ne) return;
+  int i, j, k;
+  lmk::vpos(L, p, i, j, k);
+  if (i >= nx || j >= ny || k >= nz) return;
+  float d = 0.0f;
+  if (i < nx - 1) d -= wn[p] - w[p];
+  if (i > 0) {
+    const int q = lmk::vidx(L, i - 1, j, k);
+    d += wn[q] - w[q];
+  }
+  if (j < ny - 1) d -= wn[ne + p] - w[ne + p];
+  if (j > 0) {
+    const long long q = ne + lmk::vidx(L, i, j - 1, k);
+    d += wn[q] - w[q];
+  }
+  if (ncomp == 3) {
+    if (k < nz - 1) d -= wn[2 * ne + p] - w[2 * ne + p];
+    if (k > 0) {
+      const long long q = 2 * ne + lmk::vidx(L, i, j, k - 1);
+      d += wn[q] - w[q];
+    }
+  }
+  const float zn = z[p] + d;
+  const float zb = fmaf(d, inv_p, zn);
+  z[p] = zn;
+  if (fuse)
+    x[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
+  else
+    zbar[p] = zb;
+}
+
+// Row-major image (caller layout) -> layout L, ncomp components; padding is
+// left untouched (zero).
+__global__ __launch_bounds__(kBlock) void k_to_layout(const float *__restrict__ src, float *__restrict__ dst,
+                                                      lmk::Layout L, int nx, int ny, int nz, long long ne,
+                                                      int ncomp) {
   const long long nv = (long long)nx * ny * nz;
   const long long v = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (v >= nv) return;
-  const int i = (int)(v % nx);
-  const int j = (int)((v / nx) % ny);
-  const int k = (int)(v / ((long long)nx * ny));
-  const long long sxy = (long long)nx * ny;
-  float d = 0.0f;
-  if (i < nx - 1) d -= wn[v] - w[v];
-  if (i > 0) d += wn[v - 1] - w[v - 1];
-  if (j < ny - 1) d -= wn[nv + v] - w[nv + v];
-  if (j > 0) d += wn[nv + v - nx] - w[nv + v - nx];
-  if (ncomp == 3) {
-    if (k < nz - 1) d -= wn[2 * nv + v] - w[2 * nv + v];
-    if (k > 0) d += wn[2 * nv + v - sxy] - w[2 * nv + v - sxy];
-  }
-  const float zn = z[v] + d;
-  const float zb = fmaf(d, inv_p, zn);
-  z[v] = zn;
-  if (fuse)
-    x[v] = fmaxf(0.0f, fmaf(-T[v], zb, x[v]));
-  else
-    zbar[v] = zb;
+  const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((long long)nx * ny));
+  const int q = lmk::vidx(L, i, j, k);
+  for (int c = 0; c < ncomp; ++c) dst[c * ne + q] = src[c * nv + v];
+}
+
+// Layout L -> row-major image, ncomp components.
+__global__ __launch_bounds__(kBlock) void k_from_layout(const float *__restrict__ src, float *__restrict__ dst,
+                                                        lmk::Layout L, int nx, int ny, int nz, long long ne,
+                                                        int ncomp) {
+  const long long nv = (long long)nx * ny * nz;
+  const long long v = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= nv) return;
+  const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((long long)nx * ny));
+  const int q = lmk::vidx(L, i, j, k);
+  for (int c = 0; c < ncomp; ++c) dst[c * nv + v] = src[c * ne + q];
 }
 
 // gx = K x (three components).
@@ -143,6 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_div(const float *__restrict__ w, flo
 
 namespace lmk {
 
+using lmk::Layout;
+
 int launch_primal(float *x, const float *T, const float *zbar, long long nv, hipStream_t st) {
   hipLaunchKernelGGL(k_primal, dim3(grid_for(nv)), dim3(kBlock), 0, st, x, T, zbar, nv);
   LM_TRY_HIP(hipGetLastError());
@@ -157,20 +191,36 @@ int launch_dual_image(float *z, float *dz, float *x, const float *T, float *zbar
   return LM_OK;
 }
 
-int launch_tv_dual(const int n[3], int ncomp, const float *x, const float *w, float *wn, float Sp, float beta,
-                   hipStream_t st) {
-  const long long nv = (long long)n[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_tv_dual, dim3(grid_for(nv)), dim3(kBlock), 0, st, x, w, wn, n[0], n[1], n[2], ncomp,
+int launch_tv_dual(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *wn, float Sp,
+                   float beta, hipStream_t st) {
+  const long long ne = layout_size(L);
+  hipLaunchKernelGGL(k_tv_dual, dim3(grid_for(ne)), dim3(kBlock), 0, st, x, w, wn, L, n[0], n[1], n[2], ne, ncomp,
                      Sp, beta);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
 
-int launch_tv_adjoint(const int n[3], int ncomp, const float *w, const float *wn, float *z, float *x,
-                      const float *T, float *zbar, float inv_p, bool fuse, hipStream_t st) {
+int launch_tv_adjoint(const int n[3], const Layout &L, int ncomp, const float *w, const float *wn, float *z,
+                      float *x, const float *T, float *zbar, float inv_p, bool fuse, hipStream_t st) {
+  const long long ne = layout_size(L);
+  hipLaunchKernelGGL(k_tv_adjoint, dim3(grid_for(ne)), dim3(kBlock), 0, st, w, wn, z, x, T, zbar, L, n[0], n[1],
+                     n[2], ne, ncomp, inv_p, fuse ? 1 : 0);
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+int launch_to_layout(const int n[3], const Layout &L, int ncomp, const float *src, float *dst, hipStream_t st) {
   const long long nv = (long long)n[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_tv_adjoint, dim3(grid_for(nv)), dim3(kBlock), 0, st, w, wn, z, x, T, zbar, n[0],
-                     n[1], n[2], ncomp, inv_p, fuse ? 1 : 0);
+  hipLaunchKernelGGL(k_to_layout, dim3(grid_for(nv)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2],
+                     layout_size(L), ncomp);
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+int launch_from_layout(const int n[3], const Layout &L, int ncomp, const float *src, float *dst, hipStream_t st) {
+  const long long nv = (long long)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_from_layout, dim3(grid_for(nv)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2],
+                     layout_size(L), ncomp);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }

@@ -56,7 +56,9 @@ struct lm_plan {
   lmk::GeomDev g;
   long long n = 0;       // events
   int nsub = 0;
-  long long nvox = 0;
+  long long nvox = 0;    // voxels of the image
+  lmk::Layout lay;       // brick layout of the plan's images
+  long long ne = 0;      // elements of one image in that layout (with padding)
   int ncomp = 3;         // components of w (2 for a single-slice image)
   double gamma = 0, rho = 0, beta = 0, knorm = 0, Sp = 0;
   std::vector<int> off;  // host copy of subset offsets [nsub + 1]
@@ -65,8 +67,9 @@ struct lm_plan {
   float *S = nullptr, *mu = nullptr, *P1 = nullptr, *tmp = nullptr;
   float *c = nullptr;    // complement of the dual, c = 1 - y
   int *perm = nullptr, *off_d = nullptr;
+  // images, brick layout
   float *gimg = nullptr, *T = nullptr, *z = nullptr, *zbar = nullptr, *dz = nullptr;
-  float *w = nullptr, *wn = nullptr;
+  float *w = nullptr, *wn = nullptr, *xint = nullptr;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
@@ -228,14 +231,14 @@ struct Sizes {
   size_t persistent, temporary;
 };
 
-Sizes plan_sizes(long long n, int nsub, long long nvox, int ncomp) {
+Sizes plan_sizes(long long n, int nsub, long long nvox, long long ne, int ncomp) {
   Sizes s;
-  const size_t N = (size_t)n, V = (size_t)nvox;
+  const size_t N = (size_t)n, E = (size_t)ne;
   s.persistent = N * (sizeof(int4) + 5 * sizeof(float) + sizeof(int)) + (size_t)(nsub + 1) * sizeof(int) +
-                 V * sizeof(float) * (5 + 2 * (size_t)ncomp);
+                 E * sizeof(float) * (6 + 2 * (size_t)ncomp);
   const size_t cap = hash_capacity(n);
   s.temporary = cap * (sizeof(unsigned long long) + sizeof(unsigned)) + N * sizeof(unsigned) +
-                V * sizeof(float) + 64;
+                (E + (size_t)nvox) * sizeof(float) + 64;
   return s;
 }
 
@@ -297,7 +300,7 @@ int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes) 
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(n_ev >= 0 && n_sub >= 1 && bytes, LM_EINVAL, "bad arguments");
   const int ncomp = G->n[2] > 1 ? 3 : 2;
-  const Sizes s = plan_sizes(n_ev, n_sub, lmh::nvox_of(G->n), ncomp);
+  const Sizes s = plan_sizes(n_ev, n_sub, lmh::nvox_of(G->n), lmk::layout_size(lmh::brick_layout(G->n)), ncomp);
   *bytes = s.persistent + s.temporary;
   return LM_OK;
 }
@@ -341,6 +344,9 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   p->n = n;
   p->nsub = n_sub;
   p->nvox = lmh::nvox_of(G->n);
+  p->lay = lmh::brick_layout(G->n);
+  p->ne = lmk::layout_size(p->lay);
+  p->g.lay = p->lay;  // the plan's kernels address bricked images
   p->ncomp = G->n[2] > 1 ? 3 : 2;
   p->gamma = gamma;
   p->rho = rho;
@@ -353,7 +359,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     const long long q = n / n_sub, rem = n % n_sub;
     for (int i = 0; i <= n_sub; ++i) p->off[i] = (int)(i * q + std::min<long long>(i, rem));
   }
-  const long long N = n, V = p->nvox;
+  const long long N = n, V = p->nvox, E = p->ne;
   int rc = LM_OK;
   auto fail = [&](int code) {
     free_plan(p);
@@ -362,25 +368,27 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   if ((rc = dalloc(p, &p->rec, N)) || (rc = dalloc(p, &p->S, N)) || (rc = dalloc(p, &p->mu, N)) ||
       (rc = dalloc(p, &p->c, N)) || (rc = dalloc(p, &p->P1, N)) || (rc = dalloc(p, &p->tmp, N)) ||
       (rc = dalloc(p, &p->perm, N)) || (rc = dalloc(p, &p->off_d, n_sub + 1)) ||
-      (rc = dalloc(p, &p->gimg, V)) || (rc = dalloc(p, &p->T, V)) || (rc = dalloc(p, &p->z, V)) ||
-      (rc = dalloc(p, &p->zbar, V)) || (rc = dalloc(p, &p->dz, V)) ||
-      (rc = dalloc(p, &p->w, V * p->ncomp)) || (rc = dalloc(p, &p->wn, V * p->ncomp)))
+      (rc = dalloc(p, &p->gimg, E)) || (rc = dalloc(p, &p->T, E)) || (rc = dalloc(p, &p->z, E)) ||
+      (rc = dalloc(p, &p->zbar, E)) || (rc = dalloc(p, &p->dz, E)) || (rc = dalloc(p, &p->xint, E)) ||
+      (rc = dalloc(p, &p->w, E * p->ncomp)) || (rc = dalloc(p, &p->wn, E * p->ncomp)))
     return fail(rc);
 
-  // temporaries: hash table, slots, ones image
+  // temporaries: hash table, slots, ones image (bricks), row-major image
   const unsigned long long cap = hash_capacity(N);
   unsigned long long *keys = nullptr;
   unsigned *cnt = nullptr, *slot = nullptr;
-  float *ones = nullptr;
+  float *ones = nullptr, *rowimg = nullptr;
   hipError_t e = hipMalloc(&keys, cap * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&cnt, cap * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&slot, std::max<long long>(N, 1) * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMalloc(&ones, V * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&ones, E * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&rowimg, V * sizeof(float));
   auto free_tmp = [&]() {
     if (keys) hipFree(keys);
     if (cnt) hipFree(cnt);
     if (slot) hipFree(slot);
     if (ones) hipFree(ones);
+    if (rowimg) hipFree(rowimg);
   };
   if (e != hipSuccess) {
     free_tmp();
@@ -394,6 +402,10 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     }
   };
   step(hipMemcpyAsync(p->off_d, p->off.data(), (n_sub + 1) * sizeof(int), hipMemcpyHostToDevice, st), "offsets");
+  // every image starts at zero, padding included (padding stays zero)
+  for (float *img : {p->gimg, p->T, p->z, p->zbar, p->dz, p->xint})
+    step(hipMemsetAsync(img, 0, E * sizeof(float), st), "zero images");
+  for (float *img : {p->w, p->wn}) step(hipMemsetAsync(img, 0, E * p->ncomp * sizeof(float), st), "zero w");
   if (N > 0) {
     step(hipMemsetAsync(keys, 0xFF, cap * sizeof(unsigned long long), st), "hash init");
     step(hipMemsetAsync(cnt, 0, cap * sizeof(unsigned), st), "hash init");
@@ -405,22 +417,23 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     step(hipGetLastError(), "layout");
   }
   // P^LM 1 and S
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(V)), dim3(kBlock), 0, st, ones, 1.0f, V);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, ones, 1.0f, E);
   step(hipGetLastError(), "fill");
-  if (rc == LM_OK && N > 0) rc = lmk::launch_fwd_rec(g, ones, p->rec, N, p->P1, st);
+  if (rc == LM_OK && N > 0) rc = lmk::launch_fwd_rec(p->g, ones, p->rec, N, p->P1, st);
   if (N > 0) {
     hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(gamma * rho), N);
     step(hipGetLastError(), "step S");
   }
-  // sensitivity and T
+  // sensitivity (row-major, from the caller or lm_sens) into bricks, and T
   if (g_in) {
-    step(hipMemcpyAsync(p->gimg, g_in, V * sizeof(float), hipMemcpyDeviceToDevice, st), "copy g");
+    if (rc == LM_OK) rc = lmk::launch_to_layout(G->n, p->lay, 1, g_in, p->gimg, st);
   } else {
-    step(hipMemsetAsync(p->gimg, 0, V * sizeof(float), st), "zero g");
-    if (rc == LM_OK) rc = lmk::launch_sens(g, p->gimg, st);
+    step(hipMemsetAsync(rowimg, 0, V * sizeof(float), st), "zero g");
+    if (rc == LM_OK) rc = lmk::launch_sens(g, rowimg, st);  // g: row-major geometry
+    if (rc == LM_OK) rc = lmk::launch_to_layout(G->n, p->lay, 1, rowimg, p->gimg, st);
   }
-  hipLaunchKernelGGL(k_step_T, dim3(grid_for(V)), dim3(kBlock), 0, st, p->gimg, p->T, (float)(rho / (2.0 * gamma)),
-                     (float)p->knorm, V);
+  hipLaunchKernelGGL(k_step_T, dim3(grid_for(E)), dim3(kBlock), 0, st, p->gimg, p->T, (float)(rho / (2.0 * gamma)),
+                     (float)p->knorm, E);
   step(hipGetLastError(), "step T");
   step(hipStreamSynchronize(st), "plan create");
   free_tmp();
@@ -434,18 +447,19 @@ int lm_spdhg_init(lm_plan *p, const float *x0, void *stream) {
   LM_REQUIRE(p && x0, LM_EINVAL, "NULL plan or image");
   hipStream_t st = lmh::as_stream(stream);
   p->last = st;
-  const long long N = p->n, V = p->nvox;
-  LM_TRY_HIP(hipMemcpyAsync(p->z, p->gimg, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  const long long N = p->n, E = p->ne;
+  if (int rc = lmk::launch_to_layout(p->G.n, p->lay, 1, x0, p->xint, st)) return rc;
+  LM_TRY_HIP(hipMemcpyAsync(p->z, p->gimg, E * sizeof(float), hipMemcpyDeviceToDevice, st));
   if (N > 0) {
-    if (int rc = lmk::launch_fwd_rec(p->g, x0, p->rec, N, p->c, st)) return rc;
+    if (int rc = lmk::launch_fwd_rec(p->g, p->xint, p->rec, N, p->c, st)) return rc;
     hipLaunchKernelGGL(k_init_dual, dim3(grid_for(N)), dim3(kBlock), 0, st, p->c, p->rec, p->mu, p->tmp, N);
     LM_TRY_HIP(hipGetLastError());
     if (int rc = lmk::launch_back_rec(p->g, p->tmp, p->rec, N, p->z, st)) return rc;
   }
-  LM_TRY_HIP(hipMemcpyAsync(p->zbar, p->z, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  LM_TRY_HIP(hipMemsetAsync(p->w, 0, V * p->ncomp * sizeof(float), st));
-  LM_TRY_HIP(hipMemsetAsync(p->wn, 0, V * p->ncomp * sizeof(float), st));
-  LM_TRY_HIP(hipMemsetAsync(p->dz, 0, V * sizeof(float), st));
+  LM_TRY_HIP(hipMemcpyAsync(p->zbar, p->z, E * sizeof(float), hipMemcpyDeviceToDevice, st));
+  LM_TRY_HIP(hipMemsetAsync(p->w, 0, E * p->ncomp * sizeof(float), st));
+  LM_TRY_HIP(hipMemsetAsync(p->wn, 0, E * p->ncomp * sizeof(float), st));
+  LM_TRY_HIP(hipMemsetAsync(p->dz, 0, E * sizeof(float), st));
   p->u = 0;
   p->initialized = true;
   return LM_OK;
@@ -461,37 +475,44 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
   if (n_updates == 0) return LM_OK;
   hipStream_t st = lmh::as_stream(stream);
   p->last = st;
-  const long long V = p->nvox;
+  const long long E = p->ne;
   const float inv_p_data = 2.0f * (float)p->nsub;  // 1 / p_k, p_k = 1 / (2n)
   const float inv_p_prior = 2.0f;                  // 1 / p_prior, p_prior = 1/2
-  if (int rc = timed(p, LM_K_PRIMAL, st, [&] { return lmk::launch_primal(x, p->T, p->zbar, V, st); })) return rc;
+  float *xi = p->xint;
+  if (int rc = timed(p, LM_K_PRIMAL, st, [&] {
+        int r = lmk::launch_to_layout(p->G.n, p->lay, 1, x, xi, st);
+        return r ? r : lmk::launch_primal(xi, p->T, p->zbar, E, st);
+      }))
+    return rc;
   for (int u = 0; u < n_updates; ++u) {
     const int i = seq[u];
     const bool fuse = u + 1 < n_updates;
     if (i < p->nsub) {
       const long long o = p->off[i], c = p->off[i + 1] - p->off[i];
       if (int rc = timed(p, LM_K_DATA, st, [&] {
-            return lmk::launch_data_update(p->g, x, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz, c, st);
+            return lmk::launch_data_update(p->g, xi, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz, c, st);
           }))
         return rc;
       if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
-            return lmk::launch_dual_image(p->z, p->dz, x, p->T, p->zbar, inv_p_data, fuse, V, st);
+            return lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
           }))
         return rc;
     } else {
       if (int rc = timed(p, LM_K_TV_DUAL, st, [&] {
-            return lmk::launch_tv_dual(p->G.n, p->ncomp, x, p->w, p->wn, (float)p->Sp, (float)p->beta, st);
+            return lmk::launch_tv_dual(p->G.n, p->lay, p->ncomp, xi, p->w, p->wn, (float)p->Sp, (float)p->beta, st);
           }))
         return rc;
       if (int rc = timed(p, LM_K_TV_ADJOINT, st, [&] {
-            return lmk::launch_tv_adjoint(p->G.n, p->ncomp, p->w, p->wn, p->z, x, p->T, p->zbar, inv_p_prior,
-                                          fuse, st);
+            return lmk::launch_tv_adjoint(p->G.n, p->lay, p->ncomp, p->w, p->wn, p->z, xi, p->T, p->zbar,
+                                          inv_p_prior, fuse, st);
           }))
         return rc;
       std::swap(p->w, p->wn);
     }
     ++p->u;
   }
+  if (int rc = timed(p, LM_K_PRIMAL, st, [&] { return lmk::launch_from_layout(p->G.n, p->lay, 1, xi, x, st); }))
+    return rc;
   return LM_OK;
 }
 
@@ -544,8 +565,10 @@ int lm_plan_get_images(const lm_plan *p, float *g, float *T, void *stream) {
   lmh::clear_error();
   LM_REQUIRE(p, LM_EINVAL, "NULL plan");
   hipStream_t st = lmh::as_stream(stream);
-  if (g) LM_TRY_HIP(hipMemcpyAsync(g, p->gimg, p->nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
-  if (T) LM_TRY_HIP(hipMemcpyAsync(T, p->T, p->nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (g)
+    if (int rc = lmk::launch_from_layout(p->G.n, p->lay, 1, p->gimg, g, st)) return rc;
+  if (T)
+    if (int rc = lmk::launch_from_layout(p->G.n, p->lay, 1, p->T, T, st)) return rc;
   return LM_OK;
 }
 
@@ -555,10 +578,12 @@ int lm_plan_get_state(const lm_plan *p, float *z, float *zbar, float *w, float *
   LM_REQUIRE(p->initialized, LM_ESTATE, "plan not initialised");
   hipStream_t st = lmh::as_stream(stream);
   const long long V = p->nvox;
-  if (z) LM_TRY_HIP(hipMemcpyAsync(z, p->z, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  if (zbar) LM_TRY_HIP(hipMemcpyAsync(zbar, p->zbar, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (z)
+    if (int rc = lmk::launch_from_layout(p->G.n, p->lay, 1, p->z, z, st)) return rc;
+  if (zbar)
+    if (int rc = lmk::launch_from_layout(p->G.n, p->lay, 1, p->zbar, zbar, st)) return rc;
   if (w) {
-    LM_TRY_HIP(hipMemcpyAsync(w, p->w, V * p->ncomp * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (int rc = lmk::launch_from_layout(p->G.n, p->lay, p->ncomp, p->w, w, st)) return rc;
     if (p->ncomp < 3) LM_TRY_HIP(hipMemsetAsync(w + V * p->ncomp, 0, V * (3 - p->ncomp) * sizeof(float), st));
   }
   if (c && p->n > 0) {
@@ -576,15 +601,14 @@ int lm_plan_set_state(lm_plan *p, const float *z, const float *zbar, const float
   LM_REQUIRE(u >= 0, LM_EINVAL, "negative update counter");
   hipStream_t st = lmh::as_stream(stream);
   p->last = st;
-  const long long V = p->nvox;
-  LM_TRY_HIP(hipMemcpyAsync(p->z, z, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  LM_TRY_HIP(hipMemcpyAsync(p->zbar, zbar, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  LM_TRY_HIP(hipMemcpyAsync(p->w, w, V * p->ncomp * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (int rc = lmk::launch_to_layout(p->G.n, p->lay, 1, z, p->z, st)) return rc;
+  if (int rc = lmk::launch_to_layout(p->G.n, p->lay, 1, zbar, p->zbar, st)) return rc;
+  if (int rc = lmk::launch_to_layout(p->G.n, p->lay, p->ncomp, w, p->w, st)) return rc;
   if (p->n > 0) {
     hipLaunchKernelGGL(k_gather_f, dim3(grid_for(p->n)), dim3(kBlock), 0, st, c, p->perm, p->c, p->n);
     LM_TRY_HIP(hipGetLastError());
   }
-  LM_TRY_HIP(hipMemsetAsync(p->dz, 0, V * sizeof(float), st));
+  LM_TRY_HIP(hipMemsetAsync(p->dz, 0, p->ne * sizeof(float), st));
   p->u = u;
   p->initialized = true;
   return LM_OK;

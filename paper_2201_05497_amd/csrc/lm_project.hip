@@ -55,18 +55,28 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, const float *__restri
     L = r.L;
     for (int j = lane; j < r.nplanes; j += LPE) {
       const Sample s = sample_at(g, r, j, g.tof_on);
-      acc = fmaf(s.w, gather(x, r, s), acc);
+      acc = fmaf(s.w, gather(g, x, r, s), acc);
     }
   }
   acc = group_sum<LPE>(acc);
   if (lane == 0) out[e] = L * acc;
 }
 
-template <int LPE, class Src>
-__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restrict__ v, Src src,
-                                                 long long n, float *img) {
-  const int lane = threadIdx.x % LPE;
-  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+// Per-wavefront LDS staging of the interleaved scatter (4 wavefronts per
+// block, 4 corners x 64 lanes each).
+struct Stage {
+  int idx[kBlock / 64][256];
+  float val[kBlock / 64][256];
+};
+
+// Back projection: one event per wavefront, the scatter of every 64 planes
+// interleaved over corners.
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restrict__ v, Src src, long long n,
+                                                 float *img) {
+  __shared__ Stage st;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const long long e = (long long)blockIdx.x * (kBlock / 64) + wv;
   if (e >= n) return;
   const float ve = v[e];
   if (ve == 0.0f) return;
@@ -74,19 +84,21 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restr
   if (!src.get(g, e, id1, id2, k)) return;
   const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
   const float c = r.L * ve;
-  for (int j = lane; j < r.nplanes; j += LPE) {
-    const Sample s = sample_at(g, r, j, g.tof_on);
-    if (s.w != 0.0f) scatter(img, r, s, c * s.w);
+  for (int j0 = 0; j0 < r.nplanes; j0 += 64) {
+    const int j = j0 + lane;
+    Sample s = sample_at(g, r, j, g.tof_on);
+    const float cs = (j < r.nplanes) ? c * s.w : 0.0f;
+    scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
   }
 }
 
 // Sensitivity: every unordered pair (id1 < id2) of crystals, weight summed
-// over all TOF bins.  Pair index p in [p0, p0 + np) of the row-major upper
-// triangle.
-template <int LPE>
+// over all TOF bins, one pair per wavefront.  Pair index p in [p0, p0 + np)
+// of the row-major upper triangle.
 __global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, long long p0, long long np, float *img) {
-  const int lane = threadIdx.x % LPE;
-  const long long q = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  __shared__ Stage st;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const long long q = (long long)blockIdx.x * (kBlock / 64) + wv;
   if (q >= np) return;
   const long long p = p0 + q;
   const long long nd = g.n_det;
@@ -99,47 +111,52 @@ __global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, long long p0, long l
   while (i + 1 < nd && first(i + 1) <= p) ++i;
   const long long jdx = i + 1 + (p - first(i));
   const Ray r = setup_ray(g, (int)i, (int)jdx, 0, W_SUM, 1 << 20);
-  for (int j = lane; j < r.nplanes; j += LPE) {
-    const Sample s = sample_at(g, r, j, g.tof_on);
-    if (s.w != 0.0f) scatter(img, r, s, r.L * s.w);
+  for (int j0 = 0; j0 < r.nplanes; j0 += 64) {
+    const int j = j0 + lane;
+    Sample s = sample_at(g, r, j, g.tof_on);
+    const float cs = (j < r.nplanes) ? r.L * s.w : 0.0f;
+    scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
   }
 }
 
-// Fused subset update (the data-subset branch of Algorithm 2) for the events of one
-// subset, stored contiguously in the plan's order:
+// Fused subset update (the data-subset branch of Algorithm 2) for the events
+// of one subset, stored contiguously in the plan's order, one event per
+// wavefront:
 //   q = (P x)_e + s_e;  y+ = prox(y_e + S_e q) with d = mu_e;
 //   dz += P^T((y+ - y_e)/mu_e);  y_e = y+.
 // The dual is kept as its complement c = 1 - y (y tends to 1 on LORs with
 // large expected counts, where 1 - y would cancel), and the increment is
 // evaluated in the cancellation-free form
 //   y+ - y = 2 S (q c - mu) / (S q + c + sqrt((S q - c)^2 + 4 S mu)),
-// algebraically identical to Eq. proxD minus y; c+ = c - (y+ - y).
-template <int LPE, int JMAX>
+// algebraically identical to Eq. proxD minus y; c+ = c - (y+ - y).  The
+// samples of the forward pass stay in registers for the back projection.
+template <int JMAX>
 __global__ __launch_bounds__(kBlock) void k_data_update(GeomDev g, const float *__restrict__ x,
                                                         const int4 *__restrict__ rec,
                                                         const float *__restrict__ S,
                                                         const float *__restrict__ mu,
                                                         float *__restrict__ cdual, float *dz, long long n) {
-  const int lane = threadIdx.x % LPE;
-  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
+  __shared__ Stage st;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const long long e = (long long)blockIdx.x * (kBlock / 64) + wv;
   if (e >= n) return;
   const int4 rc = rec[e];
   const float Se = S[e];
   if (Se == 0.0f) return;  // LOR misses the image: the prox leaves y unchanged
-  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, JMAX * LPE);
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, JMAX * 64);
   Sample cache[JMAX];
   float acc = 0.0f;
 #pragma unroll
   for (int jj = 0; jj < JMAX; ++jj) {
-    const int j = lane + jj * LPE;
+    const int j = lane + jj * 64;
+    cache[jj] = sample_at(g, r, j, g.tof_on);
     if (j < r.nplanes) {
-      cache[jj] = sample_at(g, r, j, g.tof_on);
-      acc = fmaf(cache[jj].w, gather(x, r, cache[jj]), acc);
+      acc = fmaf(cache[jj].w, gather(g, x, r, cache[jj]), acc);
     } else {
       cache[jj].w = 0.0f;
     }
   }
-  acc = group_sum<LPE>(acc);
+  acc = group_sum<64>(acc);
   const float q = fmaf(r.L, acc, __int_as_float(rc.w));
   const float c = cdual[e], me = mu[e];
   const float sq = Se * q;
@@ -151,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_data_update(GeomDev g, const float *
   const float cf = r.L * (dy / me);
 #pragma unroll
   for (int jj = 0; jj < JMAX; ++jj) {
-    if (cache[jj].w != 0.0f) scatter(dz, r, cache[jj], cf * cache[jj].w);
+    if (jj * 64 < r.nplanes) scatter_interleaved(g, dz, r, cache[jj], cf * cache[jj].w, lane, st.idx[wv], st.val[wv]);
   }
 }
 
@@ -216,9 +233,7 @@ int make_geom(const lm_geom *G, lmk::GeomDev *o) {
     o->h[a] = G->h[a];
     o->c0[a] = -0.5 * (G->n[a] - 1) * G->h[a];
   }
-  o->stride[0] = 1;
-  o->stride[1] = G->n[0];
-  o->stride[2] = G->n[0] * G->n[1];
+  o->lay = lmh::row_major(G->n);
   o->n_tof = G->n_tof;
   o->kmax = (G->n_tof - 1) / 2;
   o->tof_on = G->tof_on ? 1 : 0;
@@ -280,17 +295,12 @@ static int fwd_impl(const GeomDev &g, const float *x, Src src, long long n, floa
 template <class Src>
 static int back_impl(const GeomDev &g, const float *v, Src src, long long n, float *img, hipStream_t st) {
   if (n == 0) return LM_OK;
-  const int lpe = lmh::pick_launch(lmh::max_planes(g, W_BIN)).lpe;
-  return dispatch_lpe(lpe, [&](auto c) {
-    constexpr int L = decltype(c)::value;
-    for (long long o = 0; o < n; o += chunk_items(L)) {
-      const long long m = std::min(chunk_items(L), n - o);
-      hipLaunchKernelGGL((k_back<L, Src>), dim3(blocks_for(m, L)), dim3(kBlock), 0, st, g, v + o, src.offset(o), m,
-                         img);
-      LM_TRY_HIP(hipGetLastError());
-    }
-    return LM_OK;
-  });
+  for (long long o = 0; o < n; o += chunk_items(64)) {
+    const long long m = std::min(chunk_items(64), n - o);
+    hipLaunchKernelGGL((k_back<Src>), dim3(blocks_for(m, 64)), dim3(kBlock), 0, st, g, v + o, src.offset(o), m, img);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  return LM_OK;
 }
 
 int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n, float *out, hipStream_t st) {
@@ -309,11 +319,10 @@ int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long
 int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
   const long long nd = g.n_det;
   const long long npairs = nd * (nd - 1) / 2;
-  constexpr int L = 64;
-  const long long chunk = chunk_items(L);
+  const long long chunk = chunk_items(64);
   for (long long p0 = 0; p0 < npairs; p0 += chunk) {
     const long long np = std::min(chunk, npairs - p0);
-    hipLaunchKernelGGL((k_sens<L>), dim3(blocks_for(np, L)), dim3(kBlock), 0, st, g, p0, np, img);
+    hipLaunchKernelGGL(k_sens, dim3(blocks_for(np, 64)), dim3(kBlock), 0, st, g, p0, np, img);
     LM_TRY_HIP(hipGetLastError());
   }
   return LM_OK;
@@ -322,21 +331,21 @@ int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
 int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const float *S, const float *mu,
                        float *cdual, float *dz, long long n, hipStream_t st) {
   if (n == 0) return LM_OK;
-  const lmh::Launch l = lmh::pick_launch(lmh::max_planes(g, W_BIN));
-#define LM_DU(LPE_, J_)                                                                         \
-  if (l.lpe == LPE_ && l.jmax == J_) {                                                          \
-    for (long long o = 0; o < n; o += chunk_items(LPE_)) {                                      \
-      const long long m = std::min(chunk_items(LPE_), n - o);                                   \
-      hipLaunchKernelGGL((k_data_update<LPE_, J_>), dim3(blocks_for(m, LPE_)), dim3(kBlock), 0, st, g, \
-                         x, rec + o, S + o, mu + o, cdual + o, dz, m);                          \
-      LM_TRY_HIP(hipGetLastError());                                                            \
-    }                                                                                           \
-    return LM_OK;                                                                               \
+  const int planes = lmh::max_planes(g, W_BIN);
+  const int jneed = (planes + 63) / 64;
+#define LM_DU(J_)                                                                                       \
+  if (jneed <= J_) {                                                                                    \
+    for (long long o = 0; o < n; o += chunk_items(64)) {                                                \
+      const long long m = std::min(chunk_items(64), n - o);                                             \
+      hipLaunchKernelGGL((k_data_update<J_>), dim3(blocks_for(m, 64)), dim3(kBlock), 0, st, g, x, rec + o, \
+                         S + o, mu + o, cdual + o, dz, m);                                              \
+      LM_TRY_HIP(hipGetLastError());                                                                    \
+    }                                                                                                   \
+    return LM_OK;                                                                                       \
   }
-  LM_DU(32, 1) LM_DU(32, 2) LM_DU(32, 3)
-  LM_DU(64, 2) LM_DU(64, 3) LM_DU(64, 4) LM_DU(64, 6) LM_DU(64, 8)
+  LM_DU(1) LM_DU(2) LM_DU(3) LM_DU(4) LM_DU(6) LM_DU(8)
 #undef LM_DU
-  lmh::set_error("no update kernel for %d lanes x %d samples", l.lpe, l.jmax);
+  lmh::set_error("no update kernel for %d planes per event", planes);
   return LM_EINVAL;
 }
 
