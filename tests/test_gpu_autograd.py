@@ -1,0 +1,112 @@
+"""LMProject (torch.autograd.Function: forward lm_fwd, backward lm_back) on
+the differentiation workload: 16 frames of 1e6 events on 128x128x48 images
+of the 3D scanner, x ~ U[0.5, 1.5].  The gradient of the listmode Poisson
+negative log-likelihood is checked against the FP64 oracle's
+g - P^T(1 / (P x + s)) and against central finite differences (eps = 1e-3,
+loss accumulated in float64)."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import lmsynth
+import oracle
+from tests.helpers import img_err, report
+
+pytestmark = pytest.mark.gpu
+
+FRAMES = 16
+PER_FRAME = 1_000_000
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2201_05497_amd as P
+    return P
+
+
+@functools.lru_cache(maxsize=None)
+def workload():
+    p = lmsynth.simulate_3d(lmsynth.config_serving_small(), n_prompts=FRAMES * PER_FRAME, seed=1005)
+    rng = np.random.default_rng(1005)
+    x = rng.uniform(0.5, 1.5, size=(FRAMES,) + p.image.shape_zyx).astype(np.float32)
+    # a sensitivity-like input: the oracle's non-TOF P^T 1 of a decimated scanner
+    sc = p.scanner
+    dec = lmsynth.Scanner(sc.n_cry // 16, sc.n_ring // 8, sc.radius, sc.pitch * (sc.n_ring - 1) / (sc.n_ring // 8 - 1))
+    q = lmsynth.Problem("dec", dec, p.image, p.tof, 1, 1, 0.0)
+    g = oracle.sens(oracle.Geometry.from_problem(q, tof_on=False))
+    g = np.maximum(g * (sc.n_det * (sc.n_det - 1) / 2.0) / (dec.n_det * (dec.n_det - 1) / 2.0), 1.0)
+    return p, x, g.astype(np.float32)
+
+
+def _tensors(P, p, x, g):
+    G = P.Geometry.from_problem(p)
+    ev = G.events(p.events)
+    s = torch.as_tensor(p.s, device="cuda")
+    xt = torch.as_tensor(x, device="cuda")
+    gt = torch.as_tensor(g, device="cuda").expand(FRAMES, *g.shape).contiguous()
+    off = [f * PER_FRAME for f in range(FRAMES + 1)]
+    return G, ev, s, xt, gt, off
+
+
+def test_gradient_matches_oracle(P):
+    from paper_2201_05497_amd.autograd import poisson_nll
+    p, x, g = workload()
+    G, ev, s, xt, gt, off = _tensors(P, p, x, g)
+    xr = xt.clone().requires_grad_(True)
+    loss = poisson_nll(xr, G, ev, s, gt, off)
+    loss.backward()
+    grad = xr.grad.cpu().numpy()
+    Go = oracle.Geometry.from_problem(p)
+    for f in (0, FRAMES - 1):
+        e = p.events[off[f]:off[f + 1]]
+        sf = p.s[off[f]:off[f + 1]].astype(np.float64)
+        q = oracle.fwd(Go, x[f].astype(np.float64), e) + sf
+        # the data term alone (g passes through the sum unchanged and would
+        # dominate the comparison): g - grad = P^T(1 / (P x + s))
+        want = oracle.back(Go, 1.0 / q, e)
+        err = img_err(g.astype(np.float64) - grad[f].astype(np.float64), want)
+        report(f"autograd frame {f}", data_term_err=err)
+        assert err <= 1e-4
+
+
+def test_gradient_finite_differences(P):
+    from paper_2201_05497_amd.autograd import poisson_nll
+    p, x, g = workload()
+    G, ev, s, xt, gt, off = _tensors(P, p, x, g)
+    xr = xt.clone().requires_grad_(True)
+    poisson_nll(xr, G, ev, s, gt, off).backward()
+    grad = xr.grad.double()
+    rng = np.random.default_rng(77)
+    eps = 1e-3
+    worst = 0.0
+    for k in range(8):
+        d = torch.as_tensor(rng.uniform(-1.0, 1.0, size=x.shape).astype(np.float32), device="cuda")
+        with torch.no_grad():
+            lp = float(poisson_nll(xt + eps * d, G, ev, s, gt, off))
+            lm = float(poisson_nll(xt - eps * d, G, ev, s, gt, off))
+        fd = (lp - lm) / (2 * eps)
+        an = float((grad * d.double()).sum())
+        rel = abs(fd - an) / max(abs(an), 1e-12)
+        worst = max(worst, rel)
+        report(f"finite difference {k}", fd=fd, autograd=an, rel=rel)
+    assert worst <= 1e-3
+
+
+def test_single_frame_and_errors(P):
+    from paper_2201_05497_amd.autograd import LMProject
+    p, x, g = workload()
+    G = P.Geometry.from_problem(p)
+    ev = G.events(p.events[:1000])
+    x0 = torch.as_tensor(x[0], device="cuda").requires_grad_(True)
+    out = LMProject.apply(x0, G, ev)
+    assert out.shape == (1000,)
+    out.sum().backward()
+    ref = P.lm_back(G, torch.ones(1000, device="cuda"), ev)
+    assert torch.allclose(x0.grad, ref, rtol=1e-5, atol=1e-6 * float(ref.abs().max()))
+    with pytest.raises(ValueError):
+        LMProject.apply(torch.zeros((2,) + G.shape, device="cuda"), G, ev, None)
+    with pytest.raises(ValueError):
+        LMProject.apply(torch.zeros((2,) + G.shape, device="cuda"), G, ev, [0, 600, 500])

@@ -1,0 +1,90 @@
+"""The continuous-batching server: every served reconstruction equals the
+same reconstruction run alone by the plain solver (float32 atomics aside),
+admission never exceeds the HBM budget, oversized requests fail cleanly and
+waiting requests can be cancelled."""
+import numpy as np
+import pytest
+import torch
+
+import lmsynth
+from tests.helpers import img_err, report
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2201_05497_amd as P
+    return P
+
+
+def _requests(P, count=8, seed=31):
+    """Frames of a small 3D scanner on two image grids, uneven sizes."""
+    sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
+    tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
+    grids = [lmsynth.ImageGeom((48, 48, 16), (3.5, 3.5, 4.0)), lmsynth.ImageGeom((32, 32, 16), (5.0, 5.0, 4.0))]
+    geoms = []
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for grid in grids:
+        geoms.append(P.Geometry.from_problem(lmsynth.Problem("srv", sc, grid, tof, 8, 1, 0.03)))
+    for r in range(count):
+        gi = r % 2
+        n = int(10 ** rng.uniform(4, 5.3))
+        p = lmsynth.simulate_3d(lmsynth.Problem("srv", sc, grids[gi], tof, 8, 1, 0.03), n_prompts=n,
+                                seed=seed * 100 + r, workers=1)
+        reqs.append(P_serving().Request(geoms[gi], p.events, p.s, p.x0, n_subsets=8, epochs=1 + r % 2,
+                                        beta=0.03, seq_seed=1000 + r, name=f"r{r}"))
+    return reqs, geoms
+
+
+def P_serving():
+    from paper_2201_05497_amd import serving
+    return serving
+
+
+def test_served_equals_alone(P):
+    S = P_serving()
+    reqs, geoms = _requests(P)
+    alone = [S.solve(r) for r in reqs]
+    with S.Server(hbm_budget=8 << 30, max_active=4) as srv:
+        for g in geoms:
+            srv.warm(g)
+        futs = [srv.submit(r) for r in reqs]
+        res = [f.result(timeout=120) for f in futs]
+    worst = 0.0
+    for r, a, b in zip(reqs, res, alone):
+        e = img_err(a.x, b.astype(np.float64))
+        worst = max(worst, e)
+        assert a.name == r.name
+    st = S.latency_stats(res)
+    report("served vs alone", requests=len(reqs), worst=worst, p50=st["p50_s"], p99=st["p99_s"])
+    assert worst <= 1e-4
+
+
+def test_admission_budget_and_errors(P):
+    S = P_serving()
+    reqs, geoms = _requests(P, count=6, seed=32)
+    need = max(S.footprint(r) for r in reqs)
+    budget = 2 * need + sum(4 * g.nvox for g in geoms)
+    srv = S.Server(hbm_budget=budget, max_active=8)
+    for g in geoms:
+        srv.warm(g)
+    futs = [srv.submit(r) for r in reqs]
+    # a request larger than the whole budget fails without blocking the rest
+    big = reqs[0]
+    big_req = S.Request(big.geom, np.tile(big.events, (40, 1)), np.tile(big.s, 40), big.x0, n_subsets=8,
+                        epochs=1, name="big")
+    fbig = srv.submit(big_req)
+    # a waiting request can be cancelled
+    extra = srv.submit(reqs[1])
+    cancelled = extra.cancel()
+    srv.close()
+    for f in futs:
+        assert f.result().x.shape == reqs[0].x0.shape or f.result().x.ndim == 3
+    with pytest.raises(MemoryError):
+        fbig.result()
+    report("admission", budget=budget, peak=srv.peak_bytes, cancelled=int(cancelled))
+    assert srv.peak_bytes <= budget
+    assert len(srv.results) == len(reqs) + (0 if cancelled else 1)
