@@ -36,7 +36,7 @@ N_EVENTS = 10_000_000
 # algorithmic bytes per unit of each kernel class:
 #   image kernels: bytes per voxel read + written once;
 #   data update: bytes per event of the per-event lists (record, S, mu, c r/w)
-BYTES_PER_VOXEL = {"primal": 16, "dual_image": 28, "tv_dual": 28, "tv_adjoint": 44}
+BYTES_PER_VOXEL = {"primal": 16, "dual_image": 28, "tv": 44}
 BYTES_PER_EVENT = 16 + 4 + 4 + 4 + 4
 
 
@@ -89,7 +89,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event timing")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="bracket every k-th launch of each kernel class with HIP events (0: no per-kernel timing)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path is a design "
@@ -132,16 +133,16 @@ def main() -> int:
     for k in range(args.warmup):
         plan.epoch(x, seqs[k])
     torch.cuda.synchronize()
-    if not args.no_timing:
-        plan.timing(True)
+    if args.timing_every > 0:
+        plan.timing(args.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         plan.epoch(x, seqs[k])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
-    timing = plan.get_timing() if not args.no_timing else None
-    plan.timing(False)
+    timing = plan.get_timing() if args.timing_every > 0 else None
+    plan.timing(0)
 
     n_proj = sum(int(sizes[seq[seq < N_SUB]].sum()) for seq in seqs[args.warmup:])
     value = n_proj / t_total
@@ -156,12 +157,19 @@ def main() -> int:
         for k, (ms, cnt) in timing.items():
             if cnt == 0:
                 continue
-            kernels[k] = {"ms_total": ms, "launches": cnt, "us_avg": 1e3 * ms / cnt}
-        dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+            kernels[k] = {"timed_launches": cnt, "us_avg": 1e3 * ms / cnt}
+        # share of the epoch: average duration x launches of the class
+        n_data = sum(int((seq < N_SUB).sum()) for seq in seqs[args.warmup:])
+        n_prior = args.steps * 2 * N_SUB - n_data
+        launches = {"primal": 2 * args.steps, "data_update": n_data, "dual_image": n_data, "tv": n_prior}
+        for k, v in kernels.items():
+            v["launches"] = launches[k]
+            v["ms_per_step"] = round(v["us_avg"] * launches[k] / args.steps / 1e3, 3)
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         d = kernels[dom]
         if dom == "data_update":
             n_ev = n_proj
-            bytes_per_launch = BYTES_PER_EVENT * n_ev / d["launches"]
+            bytes_per_launch = BYTES_PER_EVENT * n_ev / n_data
         else:
             bytes_per_launch = BYTES_PER_VOXEL[dom] * nvox
         achieved = bytes_per_launch / (d["us_avg"] * 1e-6) / 1e9
@@ -171,7 +179,8 @@ def main() -> int:
         for k, v in kernels.items():
             if k in BYTES_PER_VOXEL:
                 v["GBs"] = round(BYTES_PER_VOXEL[k] * nvox / (v["us_avg"] * 1e-6) / 1e9, 1)
-        kernels["data_update"]["events_per_s"] = round(n_proj / (kernels["data_update"]["ms_total"] * 1e-3), 1)
+        du = kernels["data_update"]
+        du["events_per_s"] = round(n_proj / n_data / (du["us_avg"] * 1e-6), 1)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -196,18 +196,20 @@ enum {
   LM_K_PRIMAL = 0,      /* primal step at the start of a call, layout conversions of x */
   LM_K_DATA = 1,        /* fused forward / dual prox / back projection of a subset */
   LM_K_DUAL_IMAGE = 2,  /* z, zbar (and fused primal) after a data update */
-  LM_K_TV_DUAL = 3,     /* w_new = proj(w + S K x) */
-  LM_K_TV_ADJOINT = 4,  /* K^T(w_new - w), z, zbar (and fused primal) */
-  LM_K_COUNT = 5
+  LM_K_TV = 3,          /* prior update: w, K^T(w_new - w), z, zbar (and fused primal) */
+  LM_K_COUNT = 4
 };
 
-/* Per-kernel timing of lm_spdhg_epoch: while enabled, every launch of the
- * plan's update loop is bracketed by a pair of HIP events on the stream it
- * runs on.  lm_plan_get_timing (synchronous) adds the elapsed times of all
- * recorded launches to ms[LM_K_COUNT] and their number to
- * launches[LM_K_COUNT] (host arrays, accumulated since the last reset =
- * lm_plan_timing(p, 1)). */
-int lm_plan_timing(lm_plan *p, int enable);
+/* Per-kernel timing of lm_spdhg_epoch.  lm_plan_timing(p, every) resets the
+ * counters and, for every > 0, brackets every every-th launch of each kernel
+ * class of the plan's update loop (the 1st, (every+1)-th, ... since the
+ * reset) by a pair of HIP events on the stream it runs on; every = 0 turns
+ * timing off.  Sampling keeps the cost of the events (a few microseconds per
+ * bracketed launch) small against the update loop.  lm_plan_get_timing
+ * (synchronous) adds the elapsed times of the bracketed launches to
+ * ms[LM_K_COUNT] and their number to launches[LM_K_COUNT] (host arrays,
+ * accumulated since the reset).  LM_EINVAL for a negative stride. */
+int lm_plan_timing(lm_plan *p, int every);
 int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
 
 /* Frees the plan's device memory (synchronises its last stream first). */

@@ -292,16 +292,17 @@ class Plan:
                                         st["w"].data_ptr(), st["c"].data_ptr(), int(st["u"]), _stream(dev)),
                    "lm_plan_set_state")
 
-    KERNELS = ("primal", "data_update", "dual_image", "tv_dual", "tv_adjoint")
+    KERNELS = ("primal", "data_update", "dual_image", "tv")
 
-    def timing(self, enable: bool = True) -> None:
-        """Reset and enable (or disable) per-kernel timing of epoch()."""
-        _lib.check(_L.lm_plan_timing(self._handle(), int(enable)), "lm_plan_timing")
+    def timing(self, every: int = 1) -> None:
+        """Reset per-kernel timing of epoch() and time every ``every``-th
+        launch of each kernel class (0 or False: off, True: every launch)."""
+        _lib.check(_L.lm_plan_timing(self._handle(), int(every)), "lm_plan_timing")
 
     def get_timing(self):
-        """{kernel: (total ms, launches)} since the last reset (synchronises)."""
-        ms = (ctypes.c_double * 5)()
-        n = (ctypes.c_int64 * 5)()
+        """{kernel: (total ms, timed launches)} since the last reset (synchronises)."""
+        ms = (ctypes.c_double * len(self.KERNELS))()
+        n = (ctypes.c_int64 * len(self.KERNELS))()
         _lib.check(_L.lm_plan_get_timing(self._handle(), ms, n), "lm_plan_get_timing")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS)}
 

@@ -44,69 +44,201 @@ __global__ __launch_bounds__(kBlock) void k_dual_image(float *__restrict__ z, fl
     zbar[v] = zb;
 }
 
-// Prior update, part 1 (the dual prior step of Algorithm 2, R = ||.||_{2,1}):
-//   v = w + S_prior K x;  w_new = v / max(1, |v| / beta)  (pointwise norm).
-// Images use layout L (ne elements, padding skipped); w and w_new hold ncomp
-// components of ne elements each (ncomp = 2 for a single-slice image, whose
-// z-component is identically zero).
-__global__ __launch_bounds__(kBlock) void k_tv_dual(const float *__restrict__ x, const float *__restrict__ w,
-                                                    float *__restrict__ wn, lmk::Layout L, int nx, int ny, int nz,
-                                                    long long ne, int ncomp, float Sp, float beta) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= ne) return;
-  int i, j, k;
-  lmk::vpos(L, p, i, j, k);
-  if (i >= nx || j >= ny || k >= nz) return;
+// w+ - w at voxel (i, j, k): the dual prior step evaluated from x and w
+// (three components; the z-component is zero when ncomp == 2).
+__device__ __forceinline__ void tv_step_at(const float *__restrict__ x, const float *__restrict__ w,
+                                           const lmk::Layout &L, int nx, int ny, int nz, long long ne, int ncomp,
+                                           float Sp, float beta, int i, int j, int k, float &q0, float &q1,
+                                           float &q2) {
+  const int p = lmk::vidx(L, i, j, k);
   const float xv = x[p];
   const float gx = (i < nx - 1) ? x[lmk::vidx(L, i + 1, j, k)] - xv : 0.0f;
   const float gy = (j < ny - 1) ? x[lmk::vidx(L, i, j + 1, k)] - xv : 0.0f;
   const float gz = (ncomp == 3 && k < nz - 1) ? x[lmk::vidx(L, i, j, k + 1)] - xv : 0.0f;
-  const float v0 = fmaf(Sp, gx, w[p]);
-  const float v1 = fmaf(Sp, gy, w[ne + p]);
-  const float v2 = (ncomp == 3) ? fmaf(Sp, gz, w[2 * ne + p]) : 0.0f;
+  const float w0 = w[p], w1 = w[ne + p], w2 = (ncomp == 3) ? w[2 * ne + p] : 0.0f;
+  const float v0 = fmaf(Sp, gx, w0), v1 = fmaf(Sp, gy, w1), v2 = fmaf(Sp, gz, w2);
   const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
   const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
-  wn[p] = v0 * sc;
-  wn[ne + p] = v1 * sc;
-  if (ncomp == 3) wn[2 * ne + p] = v2 * sc;
+  q0 = v0 * sc - w0;
+  q1 = v1 * sc - w1;
+  q2 = v2 * sc - w2;
 }
 
-// Prior update, part 2 (the back-projection through K^T and the z / zbar
-// step of Algorithm 2, fused with the next primal step when `fuse` is set):
-//   dz = K^T (w_new - w);  z += dz;  zbar = z + dz / p;  x or zbar as above.
-__global__ __launch_bounds__(kBlock) void k_tv_adjoint(const float *__restrict__ w,
-                                                       const float *__restrict__ wn, float *__restrict__ z,
-                                                       float *__restrict__ x, const float *__restrict__ T,
-                                                       float *__restrict__ zbar, lmk::Layout L, int nx, int ny,
-                                                       int nz, long long ne, int ncomp, float inv_p, int fuse) {
+// The whole prior update in one pass (the dual prior step, its
+// back-projection through K^T and the z / zbar step of Algorithm 2, fused
+// with the next primal step when `fuse` is set):
+//   q = proj_beta(w + S_prior K x) - w;  w_out = w + q;  dz = K^T q;
+//   z += dz;  zbar = z + dz / p;  fuse ? x_out = max(0, x - T zbar) : store zbar.
+// K^T q at a voxel needs q at the voxel and at its three lower neighbours;
+// each is recomputed here from x and w (the projection couples the three
+// components), so x and w are read-only and the results go to separate
+// buffers (x_out, w_out).
+__global__ __launch_bounds__(kBlock) void k_tv_fused(const float *__restrict__ x, const float *__restrict__ w,
+                                                     float *__restrict__ w_out, float *__restrict__ z,
+                                                     float *__restrict__ x_out, const float *__restrict__ T,
+                                                     float *__restrict__ zbar, lmk::Layout L, int nx, int ny,
+                                                     int nz, long long ne, int ncomp, float Sp, float beta,
+                                                     float inv_p, int fuse) {
   const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int i, j, k;
   lmk::vpos(L, p, i, j, k);
   if (i >= nx || j >= ny || k >= nz) return;
+  float q0, q1, q2;
+  tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j, k, q0, q1, q2);
+  w_out[p] = w[p] + q0;
+  w_out[ne + p] = w[ne + p] + q1;
+  if (ncomp == 3) w_out[2 * ne + p] = w[2 * ne + p] + q2;
   float d = 0.0f;
-  if (i < nx - 1) d -= wn[p] - w[p];
+  if (i < nx - 1) d -= q0;
+  if (j < ny - 1) d -= q1;
+  if (ncomp == 3 && k < nz - 1) d -= q2;
+  float a0, a1, a2;
   if (i > 0) {
-    const int q = lmk::vidx(L, i - 1, j, k);
-    d += wn[q] - w[q];
+    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i - 1, j, k, a0, a1, a2);
+    d += a0;
   }
-  if (j < ny - 1) d -= wn[ne + p] - w[ne + p];
   if (j > 0) {
-    const long long q = ne + lmk::vidx(L, i, j - 1, k);
-    d += wn[q] - w[q];
+    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j - 1, k, a0, a1, a2);
+    d += a1;
   }
-  if (ncomp == 3) {
-    if (k < nz - 1) d -= wn[2 * ne + p] - w[2 * ne + p];
-    if (k > 0) {
-      const long long q = 2 * ne + lmk::vidx(L, i, j, k - 1);
-      d += wn[q] - w[q];
-    }
+  if (ncomp == 3 && k > 0) {
+    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j, k - 1, a0, a1, a2);
+    d += a2;
   }
   const float zn = z[p] + d;
   const float zb = fmaf(d, inv_p, zn);
   z[p] = zn;
   if (fuse)
-    x[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
+    x_out[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
+  else
+    zbar[p] = zb;
+}
+
+// The whole prior update, tiled through LDS.  A block owns a tile of
+// TBX x TBY x 1 bricks (2 x 2 bricks of 4x4x4 voxels, or 4 x 4 bricks of
+// 4x4x1 for a single slice: 256 voxels); wavefront w reads brick w of the
+// tile, so those loads are whole 256-byte bricks.  The tile stages x with a
+// one-voxel halo and computes q = proj_beta(w + S K x) - w once for the tile
+// and its lower halo (K^T q at a voxel needs q at the voxel and at its three
+// lower neighbours), then forms dz = K^T q, z, zbar and the fused primal
+// step.  Every global load of the block is issued before the first barrier.
+// Tiles are numbered so that each XCD (blocks are dealt to the 8 XCDs round
+// robin) works on one contiguous run of tiles, which keeps the halo reads of
+// neighbouring tiles in that XCD's L2.  x and w are read-only; results go to
+// x_out and w_out.
+template <int BX, int BY, int BZ, int TBX, int TBY>
+__global__ __launch_bounds__(kBlock) void k_tv_tiled(const float *__restrict__ x, const float *__restrict__ w,
+                                                     float *__restrict__ w_out, float *__restrict__ z,
+                                                     float *__restrict__ x_out, const float *__restrict__ T,
+                                                     float *__restrict__ zbar, lmk::Layout L, int nx, int ny,
+                                                     int nz, long long ne, int ncomp, float Sp, float beta,
+                                                     float inv_p, int fuse, int ntiles) {
+  constexpr int TX = TBX * BX, TY = TBY * BY, TZ = BZ;                  // tile in voxels
+  constexpr int XX = TX + 2, XY = TY + 2, XZ = (TZ > 1) ? TZ + 2 : 1;  // x with halo -1 .. +1
+  constexpr int QX = TX + 1, QY = TY + 1, QZ = (TZ > 1) ? TZ + 1 : 1;  // q with halo -1
+  constexpr int ZOFF = (TZ > 1) ? 1 : 0;
+  constexpr int NXS = XX * XY * XZ, NQ = QX * QY * QZ;
+  constexpr int RX = (NXS + kBlock - 1) / kBlock, RQ = (NQ + kBlock - 1) / kBlock;
+  constexpr int BV = BX * BY * BZ;
+  static_assert(TBX * TBY * BV == kBlock, "one voxel of the tile per thread");
+  __shared__ float xs[NXS];
+  __shared__ float qs[3][NQ];
+  int tile = blockIdx.x;
+  const int full = ntiles & ~7;
+  if (tile < full) tile = (tile & 7) * (full >> 3) + (tile >> 3);
+  const int ntx = (L.nbx + TBX - 1) / TBX, nty = (L.nby + TBY - 1) / TBY;
+  const int tbx = tile % ntx, tby = (tile / ntx) % nty, tbz = tile / (ntx * nty);
+  const int x0 = tbx * TX, y0 = tby * TY, z0 = tbz * TZ;
+  const int t = threadIdx.x;
+  // this thread's voxel: brick t / BV of the tile, voxel t % BV of the brick
+  const int b = t / BV, l = t % BV;
+  const int tx = (b % TBX) * BX + l % BX, ty = (b / TBX) * BY + (l / BX) % BY, tz = l / (BX * BY);
+  const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+  const bool mine = i < nx && j < ny && k < nz;
+  const int p = mine ? lmk::vidx(L, i, j, k) : 0;
+  // all global loads: x with halo, w on the q positions, z and T
+  float xr[RX], wr[RQ][3];
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    const int e = t + kBlock * r;
+    xr[r] = 0.0f;
+    if (e < NXS) {
+      const int ix = e % XX, iy = (e / XX) % XY, iz = e / (XX * XY);
+      const int a = x0 - 1 + ix, c = y0 - 1 + iy, d = z0 - ZOFF + iz;
+      if (a >= 0 && a < nx && c >= 0 && c < ny && d >= 0 && d < nz) xr[r] = x[lmk::vidx(L, a, c, d)];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RQ; ++r) {
+    const int e = t + kBlock * r;
+    wr[r][0] = wr[r][1] = wr[r][2] = 0.0f;
+    if (e < NQ) {
+      const int ix = e % QX, iy = (e / QX) % QY, iz = e / (QX * QY);
+      const int a = x0 - 1 + ix, c = y0 - 1 + iy, d = z0 - ZOFF + iz;
+      if (a >= 0 && a < nx && c >= 0 && c < ny && d >= 0 && d < nz) {
+        const int q = lmk::vidx(L, a, c, d);
+        wr[r][0] = w[q];
+        wr[r][1] = w[ne + q];
+        if (ncomp == 3) wr[r][2] = w[2 * ne + q];
+      }
+    }
+  }
+  const float zv = mine ? z[p] : 0.0f;
+  const float Tv = (mine && fuse) ? T[p] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < RX; ++r)
+    if (t + kBlock * r < NXS) xs[t + kBlock * r] = xr[r];
+  __syncthreads();
+  // q on the tile and its lower halo
+#pragma unroll
+  for (int r = 0; r < RQ; ++r) {
+    const int e = t + kBlock * r;
+    if (e >= NQ) break;
+    const int ix = e % QX, iy = (e / QX) % QY, iz = e / (QX * QY);
+    const int a = x0 - 1 + ix, c = y0 - 1 + iy, d = z0 - ZOFF + iz;
+    float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
+    if (a >= 0 && a < nx && c >= 0 && c < ny && d >= 0 && d < nz) {
+      const int sx = ix + XX * (iy + XY * iz);  // xs and q both start at the tile origin minus one
+      const float xv = xs[sx];
+      const float gx = (a < nx - 1) ? xs[sx + 1] - xv : 0.0f;
+      const float gy = (c < ny - 1) ? xs[sx + XX] - xv : 0.0f;
+      const float gz = (ncomp == 3 && d < nz - 1) ? xs[sx + XX * XY] - xv : 0.0f;
+      const float w0 = wr[r][0], w1 = wr[r][1], w2 = wr[r][2];
+      const float v0 = fmaf(Sp, gx, w0), v1 = fmaf(Sp, gy, w1), v2 = fmaf(Sp, gz, w2);
+      const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
+      const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
+      q0 = v0 * sc - w0;
+      q1 = v1 * sc - w1;
+      q2 = v2 * sc - w2;
+      if (ix >= 1 && iy >= 1 && iz >= ZOFF) {  // a voxel of the tile: store w+
+        const int q = lmk::vidx(L, a, c, d);
+        w_out[q] = w0 + q0;
+        w_out[ne + q] = w1 + q1;
+        if (ncomp == 3) w_out[2 * ne + q] = w2 + q2;
+      }
+    }
+    qs[0][e] = q0;
+    qs[1][e] = q1;
+    qs[2][e] = q2;
+  }
+  __syncthreads();
+  if (!mine) return;
+  const int qi = (tx + 1) + QX * ((ty + 1) + QY * (tz + ZOFF));
+  float dz = 0.0f;
+  if (i < nx - 1) dz -= qs[0][qi];
+  if (i > 0) dz += qs[0][qi - 1];
+  if (j < ny - 1) dz -= qs[1][qi];
+  if (j > 0) dz += qs[1][qi - QX];
+  if (ncomp == 3) {
+    if (k < nz - 1) dz -= qs[2][qi];
+    if (k > 0) dz += qs[2][qi - QX * QY];
+  }
+  const float zn = zv + dz;
+  const float zb = fmaf(dz, inv_p, zn);
+  z[p] = zn;
+  if (fuse)
+    x_out[p] = fmaxf(0.0f, fmaf(-Tv, zb, xs[(tx + 1) + XX * ((ty + 1) + XY * (tz + ZOFF))]));
   else
     zbar[p] = zb;
 }
@@ -191,20 +323,22 @@ int launch_dual_image(float *z, float *dz, float *x, const float *T, float *zbar
   return LM_OK;
 }
 
-int launch_tv_dual(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *wn, float Sp,
-                   float beta, hipStream_t st) {
+int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *w_out,
+                    float *z, float *x_out, const float *T, float *zbar, float Sp, float beta, float inv_p, bool fuse,
+                    hipStream_t st) {
   const long long ne = layout_size(L);
-  hipLaunchKernelGGL(k_tv_dual, dim3(grid_for(ne)), dim3(kBlock), 0, st, x, w, wn, L, n[0], n[1], n[2], ne, ncomp,
-                     Sp, beta);
-  LM_TRY_HIP(hipGetLastError());
-  return LM_OK;
-}
-
-int launch_tv_adjoint(const int n[3], const Layout &L, int ncomp, const float *w, const float *wn, float *z,
-                      float *x, const float *T, float *zbar, float inv_p, bool fuse, hipStream_t st) {
-  const long long ne = layout_size(L);
-  hipLaunchKernelGGL(k_tv_adjoint, dim3(grid_for(ne)), dim3(kBlock), 0, st, w, wn, z, x, T, zbar, L, n[0], n[1],
-                     n[2], ne, ncomp, inv_p, fuse ? 1 : 0);
+  if (L.sx == 2 && L.sy == 2 && L.sz == 2) {
+    const int ntiles = ((L.nbx + 1) / 2) * ((L.nby + 1) / 2) * L.nbz;
+    hipLaunchKernelGGL((k_tv_tiled<4, 4, 4, 2, 2>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar,
+                       L, n[0], n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0, ntiles);
+  } else if (L.sx == 2 && L.sy == 2 && L.sz == 0 && n[2] == 1) {
+    const int ntiles = ((L.nbx + 3) / 4) * ((L.nby + 3) / 4);
+    hipLaunchKernelGGL((k_tv_tiled<4, 4, 1, 4, 4>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T,
+                       zbar, L, n[0], n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0, ntiles);
+  } else {
+    hipLaunchKernelGGL(k_tv_fused, dim3(grid_for(ne)), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar, L, n[0],
+                       n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0);
+  }
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }

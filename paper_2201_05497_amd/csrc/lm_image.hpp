@@ -15,12 +15,12 @@ int launch_dual_image(float *z, float *dz, float *x, const float *T, float *zbar
                       long long nv, hipStream_t st);
 
 // Images of the prior update use layout L (padding skipped).
-// wn = proj_beta(w + Sp K x); ncomp = 3 for a 3D image, 2 when nz == 1.
-int launch_tv_dual(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *wn, float Sp,
-                   float beta, hipStream_t st);
-// dz = K^T(wn - w); z += dz; zbar = z + dz inv_p; fuse ? x update : store zbar.
-int launch_tv_adjoint(const int n[3], const Layout &L, int ncomp, const float *w, const float *wn, float *z,
-                      float *x, const float *T, float *zbar, float inv_p, bool fuse, hipStream_t st);
+// The whole prior update in one pass: w_out = proj_beta(w + Sp K x),
+// dz = K^T(w_out - w), z += dz, zbar = z + dz inv_p, fuse ? x_out = max(0,
+// x - T zbar) : store zbar.  x and w are only read (x_out, w_out separate).
+int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *w_out,
+                    float *z, float *x_out, const float *T, float *zbar, float Sp, float beta, float inv_p, bool fuse,
+                    hipStream_t st);
 
 // Conversions between the caller's row-major images (ncomp components of
 // n[0] n[1] n[2] elements) and layout L (ncomp components of layout_size(L)).

@@ -69,13 +69,14 @@ struct lm_plan {
   int *perm = nullptr, *off_d = nullptr;
   // images, brick layout
   float *gimg = nullptr, *T = nullptr, *z = nullptr, *zbar = nullptr, *dz = nullptr;
-  float *w = nullptr, *wn = nullptr, *xint = nullptr;
+  float *w = nullptr, *wn = nullptr, *xint = nullptr, *xalt = nullptr;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
   hipStream_t last = nullptr;
   // optional per-kernel timing of the update loop
-  bool timing = false;
+  int timing = 0;                                  // time every timing-th launch of a class (0: off)
+  long long t_seen[LM_K_COUNT] = {0};              // launches of each class since the reset
   std::vector<hipEvent_t> ev_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double t_ms[LM_K_COUNT] = {0};
@@ -235,7 +236,7 @@ Sizes plan_sizes(long long n, int nsub, long long nvox, long long ne, int ncomp)
   Sizes s;
   const size_t N = (size_t)n, E = (size_t)ne;
   s.persistent = N * (sizeof(int4) + 5 * sizeof(float) + sizeof(int)) + (size_t)(nsub + 1) * sizeof(int) +
-                 E * sizeof(float) * (6 + 2 * (size_t)ncomp);
+                 E * sizeof(float) * (7 + 2 * (size_t)ncomp);
   const size_t cap = hash_capacity(n);
   s.temporary = cap * (sizeof(unsigned long long) + sizeof(unsigned)) + N * sizeof(unsigned) +
                 (E + (size_t)nvox) * sizeof(float) + 64;
@@ -270,7 +271,7 @@ void free_plan(lm_plan *p) {
 // Times one launcher call when the plan's timing is enabled.
 template <class F>
 int timed(lm_plan *p, int cls, hipStream_t st, F &&launch) {
-  if (!p->timing) return launch();
+  if (!p->timing || (p->t_seen[cls]++ % p->timing) != 0) return launch();
   hipEvent_t e[2];
   for (int i = 0; i < 2; ++i) {
     if (p->ev_pool.empty()) {
@@ -370,6 +371,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
       (rc = dalloc(p, &p->perm, N)) || (rc = dalloc(p, &p->off_d, n_sub + 1)) ||
       (rc = dalloc(p, &p->gimg, E)) || (rc = dalloc(p, &p->T, E)) || (rc = dalloc(p, &p->z, E)) ||
       (rc = dalloc(p, &p->zbar, E)) || (rc = dalloc(p, &p->dz, E)) || (rc = dalloc(p, &p->xint, E)) ||
+      (rc = dalloc(p, &p->xalt, E)) ||
       (rc = dalloc(p, &p->w, E * p->ncomp)) || (rc = dalloc(p, &p->wn, E * p->ncomp)))
     return fail(rc);
 
@@ -403,7 +405,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   };
   step(hipMemcpyAsync(p->off_d, p->off.data(), (n_sub + 1) * sizeof(int), hipMemcpyHostToDevice, st), "offsets");
   // every image starts at zero, padding included (padding stays zero)
-  for (float *img : {p->gimg, p->T, p->z, p->zbar, p->dz, p->xint})
+  for (float *img : {p->gimg, p->T, p->z, p->zbar, p->dz, p->xint, p->xalt})
     step(hipMemsetAsync(img, 0, E * sizeof(float), st), "zero images");
   for (float *img : {p->w, p->wn}) step(hipMemsetAsync(img, 0, E * p->ncomp * sizeof(float), st), "zero w");
   if (N > 0) {
@@ -498,16 +500,14 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
           }))
         return rc;
     } else {
-      if (int rc = timed(p, LM_K_TV_DUAL, st, [&] {
-            return lmk::launch_tv_dual(p->G.n, p->lay, p->ncomp, xi, p->w, p->wn, (float)p->Sp, (float)p->beta, st);
-          }))
-        return rc;
-      if (int rc = timed(p, LM_K_TV_ADJOINT, st, [&] {
-            return lmk::launch_tv_adjoint(p->G.n, p->lay, p->ncomp, p->w, p->wn, p->z, xi, p->T, p->zbar,
-                                          inv_p_prior, fuse, st);
+      if (int rc = timed(p, LM_K_TV, st, [&] {
+            return lmk::launch_tv_fused(p->G.n, p->lay, p->ncomp, xi, p->w, p->wn, p->z, p->xalt, p->T, p->zbar,
+                                        (float)p->Sp, (float)p->beta, inv_p_prior, fuse, st);
           }))
         return rc;
       std::swap(p->w, p->wn);
+      if (fuse) std::swap(p->xint, p->xalt);  // the next primal step's x
+      xi = p->xint;
     }
     ++p->u;
   }
@@ -614,9 +614,10 @@ int lm_plan_set_state(lm_plan *p, const float *z, const float *zbar, const float
   return LM_OK;
 }
 
-int lm_plan_timing(lm_plan *p, int enable) {
+int lm_plan_timing(lm_plan *p, int every) {
   lmh::clear_error();
   LM_REQUIRE(p, LM_EINVAL, "NULL plan");
+  LM_REQUIRE(every >= 0, LM_EINVAL, "negative timing stride %d", every);
   for (auto &e : p->ev_pending) {
     p->ev_pool.push_back(e.second.first);
     p->ev_pool.push_back(e.second.second);
@@ -625,8 +626,9 @@ int lm_plan_timing(lm_plan *p, int enable) {
   for (int k = 0; k < LM_K_COUNT; ++k) {
     p->t_ms[k] = 0.0;
     p->t_n[k] = 0;
+    p->t_seen[k] = 0;
   }
-  p->timing = enable != 0;
+  p->timing = every;
   return LM_OK;
 }
 

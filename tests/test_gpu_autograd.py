@@ -52,24 +52,28 @@ def _tensors(P, p, x, g):
 
 
 def test_gradient_matches_oracle(P):
-    from paper_2201_05497_amd.autograd import poisson_nll
+    from paper_2201_05497_amd.autograd import LMProject, poisson_nll
     p, x, g = workload()
     G, ev, s, xt, gt, off = _tensors(P, p, x, g)
+    # the log term of the likelihood on its own (<g, x> contributes g to the
+    # gradient unchanged and would dominate the comparison)
     xr = xt.clone().requires_grad_(True)
-    loss = poisson_nll(xr, G, ev, s, gt, off)
-    loss.backward()
-    grad = xr.grad.cpu().numpy()
+    (-torch.log(LMProject.apply(xr, G, ev, off) + s).sum()).backward()
+    grad = xr.grad.cpu().numpy().astype(np.float64)
+    # and the whole likelihood: its gradient is g plus the above
+    xa = xt.clone().requires_grad_(True)
+    poisson_nll(xa, G, ev, s, gt, off).backward()
+    full = xa.grad.cpu().numpy().astype(np.float64)
     Go = oracle.Geometry.from_problem(p)
     for f in (0, FRAMES - 1):
         e = p.events[off[f]:off[f + 1]]
         sf = p.s[off[f]:off[f + 1]].astype(np.float64)
         q = oracle.fwd(Go, x[f].astype(np.float64), e) + sf
-        # the data term alone (g passes through the sum unchanged and would
-        # dominate the comparison): g - grad = P^T(1 / (P x + s))
-        want = oracle.back(Go, 1.0 / q, e)
-        err = img_err(g.astype(np.float64) - grad[f].astype(np.float64), want)
-        report(f"autograd frame {f}", data_term_err=err)
-        assert err <= 1e-4
+        want = -oracle.back(Go, 1.0 / q, e)
+        err = img_err(grad[f], want)
+        err_full = img_err(full[f], g.astype(np.float64) + want)
+        report(f"autograd frame {f}", log_term_err=err, full_err=err_full)
+        assert err <= 1e-4 and err_full <= 1e-4
 
 
 def test_gradient_finite_differences(P):

@@ -297,3 +297,37 @@ def test_empty_subsets_match_oracle(P):
     Gg, plan = _plan(P, p, 8, sens_2d(), 0.03, events=ev, s=s)
     _run_compare(P, p, Gg, plan, sens_2d().astype(np.float32).astype(np.float64), 8, 0.03, 2, 7, "empty subsets",
                  events=ev, s=s)
+
+
+def test_kernel_timing_sampling(P):
+    """lm_plan_timing(p, k) brackets every k-th launch of each kernel class;
+    timing changes nothing in the iterates."""
+    p = problem_2d()
+    n = 28
+    seq = lmsynth.subset_sequence(7, 0, 2 * n, n)
+    xs = []
+    counts = {}
+    for every in (0, 1, 3):
+        Gg, plan = _plan(P, p, n, sens_2d(), 0.03)
+        x = torch.as_tensor(p.x0, device="cuda").clone()
+        plan.init(x)
+        plan.timing(every)
+        plan.epoch(x, seq)
+        t = plan.get_timing()
+        xs.append(x.cpu().numpy())
+        counts[every] = {k: c for k, (ms, c) in t.items()}
+        if every == 0:
+            assert all(c == 0 and ms == 0.0 for ms, c in t.values())
+        else:
+            assert all(ms > 0.0 for ms, c in t.values() if c > 0)
+        with pytest.raises(P.LMError):
+            plan.timing(-1)
+        plan.destroy()
+    n_data = int((seq < n).sum())
+    n_prior = len(seq) - n_data
+    assert counts[1]["data_update"] == n_data and counts[1]["dual_image"] == n_data
+    assert counts[1]["tv"] == n_prior
+    for k, c in counts[1].items():
+        assert counts[3][k] == (c + 2) // 3, (k, c, counts[3][k])
+    # atomics make runs differ in the last bits only
+    assert img_err(xs[1], xs[0]) <= 1e-5 and img_err(xs[2], xs[0]) <= 1e-5
