@@ -80,6 +80,14 @@ const char *lm_last_error(void);
 
 /* ---------------------------------------------------------------- projector */
 
+/* Images passed to the projector calls are row-major float[nz][ny][nx]
+ * device arrays.  Each call copies the image into a temporary in the
+ * library's 4x4x4-voxel brick layout (stream-ordered hipMallocAsync on
+ * `stream`, freed stream-ordered before the call returns; LM_ENOMEM if it
+ * cannot be allocated), runs on the copy, and for lm_back / lm_sens writes
+ * the result back.  All work is queued on `stream` (NULL: the default
+ * stream); the calls do not synchronise. */
+
 /* Listmode forward projection (Eq. lmop): out[e] = (P^LM x)_e for the n
  * events ev[n][5] in the caller's order.  x: image; out: float[n]. */
 int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out,

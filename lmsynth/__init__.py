@@ -290,6 +290,7 @@ def _tof_bins(P, det64, c1, r1, c2, r2, sc: Scanner, tof: TOF, rng):
     p1, p2 = det64[i1], det64[i2]
     d = p2 - p1
     nrm = np.linalg.norm(d, axis=1)
+    nrm = np.where(nrm > 0.0, nrm, 1.0)  # same-crystal pairs: dropped by the caller
     t = np.einsum("ij,ij->i", P - 0.5 * (p1 + p2), d) / nrm
     t = t + rng.normal(0.0, tof.sigma, size=t.shape)
     return np.rint(t / tof.bin).astype(np.int64)

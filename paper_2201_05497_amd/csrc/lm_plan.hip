@@ -239,7 +239,7 @@ Sizes plan_sizes(long long n, int nsub, long long nvox, long long ne, int ncomp)
                  E * sizeof(float) * (7 + 2 * (size_t)ncomp);
   const size_t cap = hash_capacity(n);
   s.temporary = cap * (sizeof(unsigned long long) + sizeof(unsigned)) + N * sizeof(unsigned) +
-                (E + (size_t)nvox) * sizeof(float) + 64;
+                E * sizeof(float) + 64;
   return s;
 }
 
@@ -360,7 +360,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     const long long q = n / n_sub, rem = n % n_sub;
     for (int i = 0; i <= n_sub; ++i) p->off[i] = (int)(i * q + std::min<long long>(i, rem));
   }
-  const long long N = n, V = p->nvox, E = p->ne;
+  const long long N = n, E = p->ne;
   int rc = LM_OK;
   auto fail = [&](int code) {
     free_plan(p);
@@ -375,22 +375,20 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
       (rc = dalloc(p, &p->w, E * p->ncomp)) || (rc = dalloc(p, &p->wn, E * p->ncomp)))
     return fail(rc);
 
-  // temporaries: hash table, slots, ones image (bricks), row-major image
+  // temporaries: hash table, slots, ones image (bricks)
   const unsigned long long cap = hash_capacity(N);
   unsigned long long *keys = nullptr;
   unsigned *cnt = nullptr, *slot = nullptr;
-  float *ones = nullptr, *rowimg = nullptr;
+  float *ones = nullptr;
   hipError_t e = hipMalloc(&keys, cap * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&cnt, cap * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&slot, std::max<long long>(N, 1) * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&ones, E * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&rowimg, V * sizeof(float));
   auto free_tmp = [&]() {
     if (keys) hipFree(keys);
     if (cnt) hipFree(cnt);
     if (slot) hipFree(slot);
     if (ones) hipFree(ones);
-    if (rowimg) hipFree(rowimg);
   };
   if (e != hipSuccess) {
     free_tmp();
@@ -430,9 +428,8 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   if (g_in) {
     if (rc == LM_OK) rc = lmk::launch_to_layout(G->n, p->lay, 1, g_in, p->gimg, st);
   } else {
-    step(hipMemsetAsync(rowimg, 0, V * sizeof(float), st), "zero g");
-    if (rc == LM_OK) rc = lmk::launch_sens(g, rowimg, st);  // g: row-major geometry
-    if (rc == LM_OK) rc = lmk::launch_to_layout(G->n, p->lay, 1, rowimg, p->gimg, st);
+    step(hipMemsetAsync(p->gimg, 0, E * sizeof(float), st), "zero g");
+    if (rc == LM_OK) rc = lmk::launch_sens(p->g, p->gimg, st);  // bricked geometry
   }
   hipLaunchKernelGGL(k_step_T, dim3(grid_for(E)), dim3(kBlock), 0, st, p->gimg, p->T, (float)(rho / (2.0 * gamma)),
                      (float)p->knorm, E);

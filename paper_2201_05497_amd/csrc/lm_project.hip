@@ -15,6 +15,7 @@
 
 #include "lm_device.hpp"
 #include "lm_host.hpp"
+#include "lm_image.hpp"
 
 using namespace lmk;
 
@@ -351,6 +352,31 @@ int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const 
 
 }  // namespace lmk
 
+// The plain projector calls run on a bricked copy of the caller's row-major
+// image (the layout of the plans, 4x4x4 voxels per brick): gathers and the
+// interleaved scatter then touch few cache lines per instruction.  The copy
+// is a stream-ordered temporary freed (stream-ordered) when the call
+// returns; its padding voxels are never read or written, since every
+// corner is checked against the image size.
+struct BrickImage {
+  float *p = nullptr;
+  hipStream_t st = nullptr;
+  int alloc(GeomDev &g, hipStream_t s) {
+    g.lay = lmh::brick_layout(g.n);
+    st = s;
+    const hipError_t e = hipMallocAsync((void **)&p, (size_t)layout_size(g.lay) * sizeof(float), s);
+    if (e != hipSuccess) {
+      p = nullptr;
+      lmh::set_error("image temporary: %s", hipGetErrorString(e));
+      return LM_ENOMEM;
+    }
+    return LM_OK;
+  }
+  ~BrickImage() {
+    if (p) hipFreeAsync(p, st);
+  }
+};
+
 // --------------------------------------------------------------------------
 // C ABI
 
@@ -362,7 +388,12 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(n >= 0, LM_EINVAL, "negative event count");
   LM_REQUIRE(n == 0 || (x && ev && out), LM_EINVAL, "NULL array");
-  return launch_fwd(g, x, ev, n, out, lmh::as_stream(stream));
+  if (n == 0) return LM_OK;
+  hipStream_t st = lmh::as_stream(stream);
+  BrickImage b;
+  if (int rc = b.alloc(g, st)) return rc;
+  if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, x, b.p, st)) return rc;
+  return launch_fwd(g, b.p, ev, n, out, st);
 }
 
 int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img, void *stream) {
@@ -371,7 +402,13 @@ int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, floa
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(n >= 0, LM_EINVAL, "negative event count");
   LM_REQUIRE(n == 0 || (v && ev && img), LM_EINVAL, "NULL array");
-  return launch_back(g, v, ev, n, img, lmh::as_stream(stream));
+  if (n == 0) return LM_OK;
+  hipStream_t st = lmh::as_stream(stream);
+  BrickImage b;
+  if (int rc = b.alloc(g, st)) return rc;
+  if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, img, b.p, st)) return rc;
+  if (int rc = launch_back(g, v, ev, n, b.p, st)) return rc;
+  return lmk::launch_from_layout(g.n, g.lay, 1, b.p, img, st);
 }
 
 int lm_sens(const lm_geom *G, float *img, void *stream) {
@@ -379,7 +416,12 @@ int lm_sens(const lm_geom *G, float *img, void *stream) {
   GeomDev g;
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(img != nullptr, LM_EINVAL, "NULL image");
-  return launch_sens(g, img, lmh::as_stream(stream));
+  hipStream_t st = lmh::as_stream(stream);
+  BrickImage b;
+  if (int rc = b.alloc(g, st)) return rc;
+  if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, img, b.p, st)) return rc;
+  if (int rc = launch_sens(g, b.p, st)) return rc;
+  return lmk::launch_from_layout(g.n, g.lay, 1, b.p, img, st);
 }
 
 int lm_validate_events(const lm_geom *G, const int16_t *ev, int64_t n, int64_t *n_bad, void *stream) {
