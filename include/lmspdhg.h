@@ -145,8 +145,10 @@ int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes);
  * sensitivity image or NULL (then lm_sens is run); knorm <= 0 selects the
  * exact norm of K, sqrt(sum_a 4 sin^2(pi (N_a-1) / (2 N_a))).  The plan
  * keeps a copy of G (det must stay valid) and owns all its device memory
- * until lm_plan_destroy.  Work runs on `stream`; the call returns after it
- * finished. */
+ * until lm_plan_destroy; it allocates stream-ordered (hipMallocAsync on
+ * `stream`, from the device's default memory pool), so creating or
+ * destroying a plan never waits for work on other streams.  Work runs on
+ * `stream`; the call returns after it finished. */
 int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int32_t n_sub,
                    const float *g, double gamma, double rho, double beta, double knorm, void *stream,
                    lm_plan **out);
@@ -220,7 +222,8 @@ enum {
 int lm_plan_timing(lm_plan *p, int every);
 int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
 
-/* Frees the plan's device memory (synchronises its last stream first). */
+/* Synchronises the plan's last stream, then frees its device memory
+ * stream-ordered on that stream (hipFreeAsync: no device-wide wait). */
 int lm_plan_destroy(lm_plan *p);
 
 #ifdef __cplusplus

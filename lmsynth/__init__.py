@@ -429,7 +429,7 @@ def _contamination_level(rng, sc: Scanner, tof: TOF, n_contam: int, smooth: bool
 
 
 def _finish(rng, trues, contam, s_true_level, s_contam, p: Problem, seed: int):
-    ev = np.concatenate([trues, contam]).astype(np.int64)
+    ev = np.concatenate([trues, contam])
     s_all = np.concatenate([s_true_level, s_contam])
     order = rng.permutation(len(ev))
     p.events = np.ascontiguousarray(ev[order].astype(np.int16))
@@ -459,11 +459,17 @@ CHUNK = 500_000  # events per independently seeded generation chunk
 
 
 def _chunk(task):
+    """One chunk of 3D events: (int16 [m, 5] events, float64 [m] distance
+    of each LOR from the scanner axis)."""
     kind, count, seed_seq, sc, tof = task
     rng = np.random.default_rng(seed_seq)
     if kind == "t":
-        return _trues(rng, count, sc, tof, 3)
-    return _contamination(rng, count, sc, tof, smooth=True)
+        ev = _trues(rng, count, sc, tof, 3)
+    else:
+        ev = _contamination(rng, count, sc, tof, smooth=True)
+    det64 = det_table(sc).astype(np.float64)
+    b = _lor_axis_distance(det64, ev[:, 0], ev[:, 1], ev[:, 2], ev[:, 3], sc)
+    return ev.astype(np.int16), b
 
 
 def _chunked(kind: str, n: int, seed_seq, sc: Scanner, tof: TOF):
@@ -472,13 +478,14 @@ def _chunked(kind: str, n: int, seed_seq, sc: Scanner, tof: TOF):
 
 
 def simulate_3d(p: Problem, n_prompts: int = 10_000_000, contam_frac: float = 0.3,
-                seed: int = 1001, workers: int | None = None) -> Problem:
+                seed: int = 1001, workers: int | None = None, progress=None) -> Problem:
     """Prompts of the 3D ellipsoid phantom: trues by Monte Carlo (isotropic
     directions accepted when both ends hit the crystal cylinder), plus
     contamination whose per-bin expectation is a smooth Gaussian profile in
     the LOR's distance from the axis; s_e is that expectation.  Generated in
     chunks of CHUNK events with seeds spawned from `seed`, so the result does
-    not depend on the number of worker processes."""
+    not depend on the number of worker processes.  `progress(msg)`, if given,
+    is called about every tenth of the chunks."""
     import os
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
@@ -490,24 +497,38 @@ def simulate_3d(p: Problem, n_prompts: int = 10_000_000, contam_frac: float = 0.
     tasks = _chunked("t", n_t, s_t, p.scanner, p.tof) + _chunked("c", n_c, s_c, p.scanner, p.tof)
     if workers is None:
         workers = min(len(tasks), os.cpu_count() or 1, 16)
+    every = max(1, len(tasks) // 10)
+
+    def collect(it):
+        out = []
+        for i, r in enumerate(it):
+            out.append(r)
+            if progress is not None and ((i + 1) % every == 0 or i + 1 == len(tasks)):
+                progress(f"generated {i + 1} of {len(tasks)} chunks of {CHUNK} events")
+        return out
+
     res = None
     if workers > 1 and len(tasks) > 1:
         try:
             with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-                res = list(ex.map(_chunk, tasks))
+                res = collect(ex.map(_chunk, tasks))
         except (RuntimeError, OSError):
             # e.g. a calling script without a __main__ guard: generate serially
             res = None
     if res is None:
-        res = [_chunk(t) for t in tasks]
+        res = collect(map(_chunk, tasks))
     nt_chunks = len(_chunked("t", n_t, s_t, p.scanner, p.tof))
-    trues = np.concatenate(res[:nt_chunks]) if nt_chunks else np.empty((0, 5), np.int64)
-    contam = np.concatenate(res[nt_chunks:]) if len(res) > nt_chunks else np.empty((0, 5), np.int64)
+
+    def cat(parts, j, shape, dtype):
+        return np.concatenate([r[j] for r in parts]) if parts else np.empty(shape, dtype)
+
+    trues = cat(res[:nt_chunks], 0, (0, 5), np.int16)
+    contam = cat(res[nt_chunks:], 0, (0, 5), np.int16)
+    b = np.concatenate([cat(res[:nt_chunks], 1, (0,), np.float64), cat(res[nt_chunks:], 1, (0,), np.float64)])
+    del res
     s0 = _contamination_level(rng, p.scanner, p.tof, n_c, smooth=True)
-    det64 = det_table(p.scanner).astype(np.float64)
-    ev_all = np.concatenate([trues, contam])
-    b = _lor_axis_distance(det64, ev_all[:, 0], ev_all[:, 1], ev_all[:, 2], ev_all[:, 3], p.scanner)
     s = s0 * np.exp(-b * b / (2 * SCATTER_WIDTH ** 2))
+    del b
     p.x0 = uniform_x0(p, n_t, radius=0.9 * 0.5 * p.image.n[0] * p.image.h[0], rng=rng)
     return _finish(rng, trues, contam, s[:n_t], s[n_t:], p, seed)
 

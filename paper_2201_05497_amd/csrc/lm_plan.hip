@@ -247,9 +247,9 @@ template <class T>
 int dalloc(lm_plan *p, T **ptr, size_t count) {
   void *q = nullptr;
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  const hipError_t e = hipMalloc(&q, bytes);
+  const hipError_t e = hipMallocAsync(&q, bytes, p->last);
   if (e != hipSuccess) {
-    lmh::set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    lmh::set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     return LM_ENOMEM;
   }
   p->allocs.push_back(q);
@@ -257,8 +257,11 @@ int dalloc(lm_plan *p, T **ptr, size_t count) {
   return LM_OK;
 }
 
+// Device memory is allocated and freed stream-ordered (hipMallocAsync /
+// hipFreeAsync on the plan's last stream): neither implies a device-wide
+// synchronisation, so plans of other streams keep running meanwhile.
 void free_plan(lm_plan *p) {
-  for (void *q : p->allocs) hipFree(q);
+  for (void *q : p->allocs) hipFreeAsync(q, p->last);
   p->allocs.clear();
   for (auto &e : p->ev_pending) {
     hipEventDestroy(e.second.first);
@@ -325,7 +328,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   // validate before allocating anything
   if (n > 0) {
     unsigned long long *bad = nullptr;
-    LM_TRY_HIP(hipMalloc(&bad, sizeof(unsigned long long)));
+    LM_TRY_HIP(hipMallocAsync((void **)&bad, sizeof(unsigned long long), st));
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), st);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(k_count_bad, dim3(grid_for(n)), dim3(kBlock), 0, st, g, ev, (long long)n, bad);
@@ -334,7 +337,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     unsigned long long hb = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(bad);
+    hipFreeAsync(bad, st);
     LM_TRY_HIP(e);
     LM_REQUIRE(hb == 0, LM_ERANGE, "%llu events have a crystal, ring or TOF index out of range", hb);
   }
@@ -380,15 +383,15 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   unsigned long long *keys = nullptr;
   unsigned *cnt = nullptr, *slot = nullptr;
   float *ones = nullptr;
-  hipError_t e = hipMalloc(&keys, cap * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc(&cnt, cap * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMalloc(&slot, std::max<long long>(N, 1) * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMalloc(&ones, E * sizeof(float));
+  hipError_t e = hipMallocAsync((void **)&keys, cap * sizeof(unsigned long long), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, cap * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&slot, std::max<long long>(N, 1) * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&ones, E * sizeof(float), st);
   auto free_tmp = [&]() {
-    if (keys) hipFree(keys);
-    if (cnt) hipFree(cnt);
-    if (slot) hipFree(slot);
-    if (ones) hipFree(ones);
+    if (keys) hipFreeAsync(keys, st);
+    if (cnt) hipFreeAsync(cnt, st);
+    if (slot) hipFreeAsync(slot, st);
+    if (ones) hipFreeAsync(ones, st);
   };
   if (e != hipSuccess) {
     free_tmp();

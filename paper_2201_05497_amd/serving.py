@@ -9,7 +9,9 @@ and the scheduler issues one epoch per request per tick, so kernels of
 different requests overlap on the device.  Admission is first come, first
 served against an HBM budget, using lm_plan_bytes for the plan's footprint
 plus the request's own inputs.  Sensitivity images are computed once per
-scanner and image geometry (lm_sens) and shared.
+scanner and image geometry (lm_sens) and shared.  Plans allocate
+stream-ordered, so admitting or finishing a request never waits for the
+work of the others.
 
 Every step of a reconstruction runs in the library's kernels; this module
 only schedules them.  The method is unchanged: a served reconstruction is
@@ -92,9 +94,11 @@ class _SensCache:
         self._c: Dict[tuple, torch.Tensor] = {}
         self._lock = threading.Lock()
 
-    def get(self, geom: Geometry) -> torch.Tensor:
+    def get(self, geom: Geometry, g: Optional[torch.Tensor] = None) -> torch.Tensor:
         key = _geom_key(geom)
         with self._lock:
+            if key not in self._c and g is not None:
+                self._c[key] = g
             if key not in self._c:
                 s = torch.cuda.Stream(device=geom.device)
                 with torch.cuda.stream(s):
@@ -129,9 +133,9 @@ class _Active:
         self.inputs = ()
         self.seq = None
         self.issued = 0
-        self.last_event = None
+        self.pending: collections.deque = collections.deque()  # events of queued epochs
         self.bytes = 0
-        self.cancelled = False
+        self.error: Optional[BaseException] = None
 
 
 class Server:
@@ -139,18 +143,29 @@ class Server:
 
     hbm_budget: device bytes the resident reconstructions may hold (shared
     sensitivity images included; the scheduler thread alone updates the
-    plans' share).  max_active: most reconstructions resident
-    at once.  A request whose footprint alone exceeds the budget fails with
-    MemoryError.  ``close()`` waits for the admitted and queued work."""
+    plans' share).  max_active: most reconstructions admitted at once (being
+    prepared or running).  epochs_in_flight: epochs queued ahead on each
+    request's stream.  A request whose footprint alone exceeds the budget
+    fails with MemoryError.  ``close()`` waits for the admitted and queued
+    work.
 
-    def __init__(self, hbm_budget: int, device="cuda:0", max_active: int = 8, epochs_in_flight: int = 1):
+    Two threads: the scheduler admits requests, issues epochs and completes
+    results; a preparation thread uploads each admitted request's inputs
+    and builds its plan (plan creation is synchronous on the request's own
+    stream), so that the scheduler keeps the running requests fed
+    meanwhile."""
+
+    def __init__(self, hbm_budget: int, device="cuda:0", max_active: int = 8, epochs_in_flight: int = 2):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.in_flight = max(1, int(epochs_in_flight))
         self._q: "queue.Queue[tuple]" = queue.Queue()
+        self._prep_q: "queue.Queue[Optional[_Active]]" = queue.Queue()
+        self._ready: "queue.Queue[_Active]" = queue.Queue()
         self._waiting: collections.deque = collections.deque()
         self._active: List[_Active] = []
+        self._preparing = 0
         self._sens = _SensCache()
         self._used = 0
         self.peak_bytes = 0
@@ -158,14 +173,16 @@ class Server:
         self._stop = False
         self._err: Optional[BaseException] = None
         self._thread = threading.Thread(target=self._loop, name="lm-serving", daemon=True)
+        self._prep = threading.Thread(target=self._prep_loop, name="lm-serving-prep", daemon=True)
+        self._prep.start()
         self._thread.start()
 
     # ------------------------------------------------------------ client API
 
-    def warm(self, geom: Geometry) -> None:
-        """Compute (and keep) the sensitivity image of a geometry before
-        requests for it arrive."""
-        self._sens.get(geom)
+    def warm(self, geom: Geometry, g: Optional[torch.Tensor] = None) -> None:
+        """Compute (or take g as) the sensitivity image of a geometry and
+        keep it, before requests for it arrive."""
+        self._sens.get(geom, g)
 
     def submit(self, req: Request) -> Future:
         if self._stop:
@@ -178,6 +195,7 @@ class Server:
         self._stop = True
         if wait:
             self._thread.join()
+            self._prep.join()
         if self._err is not None:
             raise RuntimeError("serving loop failed") from self._err
 
@@ -194,10 +212,12 @@ class Server:
             torch.cuda.set_device(self.device)
             while True:
                 self._drain_queue()
+                self._collect_ready()
                 self._admit()
                 progressed = self._tick()
-                self._complete()
-                if self._stop and not self._waiting and not self._active and self._q.empty():
+                progressed |= self._complete()
+                if (self._stop and not self._waiting and not self._active and not self._preparing
+                        and self._q.empty()):
                     break
                 if not progressed:
                     time.sleep(0.0002)
@@ -207,6 +227,8 @@ class Server:
                 fut = a.fut if isinstance(a, _Active) else a[1]
                 if not fut.done():
                     fut.set_exception(e)
+        finally:
+            self._prep_q.put(None)
 
     def _drain_queue(self):
         while True:
@@ -217,7 +239,7 @@ class Server:
             self._waiting.append((req, fut, t))
 
     def _admit(self):
-        while self._waiting and len(self._active) < self.max_active:
+        while self._waiting and len(self._active) + self._preparing < self.max_active:
             req, fut, t = self._waiting[0]
             if fut.cancelled():
                 self._waiting.popleft()
@@ -238,76 +260,110 @@ class Server:
             a.bytes = need
             self._used += need
             self.peak_bytes = max(self.peak_bytes, self._used + shared + need_sens)
-            self._start(a)
-            self._active.append(a)
+            self._preparing += 1
+            self._prep_q.put(a)
+
+    def _prep_loop(self):
+        torch.cuda.set_device(self.device)
+        while True:
+            a = self._prep_q.get()
+            if a is None:
+                return
+            try:
+                self._start(a)
+            except BaseException as e:
+                a.error = e
+            self._ready.put(a)
 
     def _start(self, a: _Active):
+        """Preparation thread: inputs to the device, plan, initialisation."""
         req = a.req
         a.t_admit = time.perf_counter()
         g = self._sens.get(req.geom)
         a.stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(a.stream):
-            ev = torch.from_numpy(np.ascontiguousarray(req.events, dtype=np.int16)).pin_memory().to(
-                self.device, non_blocking=True)
-            s = torch.from_numpy(np.ascontiguousarray(req.s, dtype=np.float32)).pin_memory().to(
-                self.device, non_blocking=True)
-            a.x = torch.from_numpy(np.ascontiguousarray(req.x0, dtype=np.float32)).pin_memory().to(
-                self.device, non_blocking=True)
+            ev = torch.from_numpy(np.ascontiguousarray(req.events, dtype=np.int16)).to(self.device)
+            s = torch.from_numpy(np.ascontiguousarray(req.s, dtype=np.float32)).to(self.device)
+            a.x = torch.from_numpy(np.ascontiguousarray(req.x0, dtype=np.float32)).to(self.device)
             a.plan = Plan(req.geom, ev, s, req.n_subsets, _gamma(req), req.rho, req.beta, g=g)
             a.plan.init(a.x)
         a.inputs = (ev, s)
         a.seq = req.sequence()
 
+    def _collect_ready(self):
+        while True:
+            try:
+                a = self._ready.get_nowait()
+            except queue.Empty:
+                return
+            self._preparing -= 1
+            if a.error is not None:
+                self._release(a)
+                if not a.fut.done():
+                    a.fut.set_exception(a.error)
+                continue
+            self._active.append(a)
+
     def _tick(self) -> bool:
         progressed = False
         for a in self._active:
-            if a.fut.cancelled() or a.cancelled:
+            if a.fut.cancelled():
                 continue
+            while a.pending and a.pending[0].query():
+                a.pending.popleft()
             step = 2 * a.req.n_subsets
-            if a.issued >= len(a.seq):
-                continue
-            # keep at most `in_flight` epochs queued per request
-            if a.last_event is not None and self.in_flight == 1 and not a.last_event.query():
-                continue
-            with torch.cuda.stream(a.stream):
-                a.plan.epoch(a.x, a.seq[a.issued:a.issued + step])
-                a.last_event = torch.cuda.Event()
-                a.last_event.record(a.stream)
-            a.issued += step
-            progressed = True
+            # keep up to `in_flight` epochs queued on the request's stream
+            while a.issued < len(a.seq) and len(a.pending) < self.in_flight:
+                with torch.cuda.stream(a.stream):
+                    a.plan.epoch(a.x, a.seq[a.issued:a.issued + step])
+                    ev = torch.cuda.Event()
+                    ev.record(a.stream)
+                a.pending.append(ev)
+                a.issued += step
+                progressed = True
         return progressed
 
-    def _complete(self):
+    def _release(self, a: _Active):
+        if a.plan is not None:
+            a.plan.destroy()
+        a.plan = a.x = None
+        a.inputs = ()
+        self._used -= a.bytes
+
+    def _complete(self) -> bool:
         keep = []
+        done_any = False
         for a in self._active:
-            done = a.issued >= len(a.seq) and (a.last_event is None or a.last_event.query())
+            done = a.issued >= len(a.seq) and all(e.query() for e in a.pending)
             if a.fut.cancelled():
                 done = True
             if not done:
                 keep.append(a)
                 continue
+            done_any = True
             a.stream.synchronize()
             if not a.fut.cancelled():
-                x = a.x.cpu().numpy()
+                with torch.cuda.stream(a.stream):
+                    x = a.x.cpu().numpy()
                 res = Result(a.req.name, x, len(a.req.events), a.req.epochs, a.t_submit, a.t_admit,
                              time.perf_counter())
                 self.results.append(res)
                 a.fut.set_result(res)
-            a.plan.destroy()
-            a.plan = a.x = None
-            a.inputs = ()
-            self._used -= a.bytes
+            self._release(a)
         self._active = keep
+        return done_any
 
 
-def solve(req: Request, device="cuda:0") -> np.ndarray:
+def solve(req: Request, device="cuda:0", g: Optional[torch.Tensor] = None) -> np.ndarray:
     """The plain solver: one reconstruction on the current stream, start to
-    finish (the baseline the server is compared with)."""
+    finish (the baseline the server is compared with).  g: the sensitivity
+    image of the request's geometry if already computed (else lm_sens)."""
     dev = torch.device(device)
     ev = torch.from_numpy(np.ascontiguousarray(req.events, dtype=np.int16)).to(dev)
     s = torch.from_numpy(np.ascontiguousarray(req.s, dtype=np.float32)).to(dev)
     x = torch.from_numpy(np.ascontiguousarray(req.x0, dtype=np.float32)).to(dev)
-    g = lm_sens(req.geom)
+    if g is None:
+        g = lm_sens(req.geom)
     with Plan(req.geom, ev, s, req.n_subsets, _gamma(req), req.rho, req.beta, g=g) as plan:
         plan.init(x)
         plan.epoch(x, req.sequence())

@@ -88,3 +88,24 @@ def test_admission_budget_and_errors(P):
     report("admission", budget=budget, peak=srv.peak_bytes, cancelled=int(cancelled))
     assert srv.peak_bytes <= budget
     assert len(srv.results) == len(reqs) + (0 if cancelled else 1)
+
+
+def test_failed_preparation_fails_alone(P):
+    """A request whose plan cannot be built (an event index out of range)
+    fails with the library's error; the others complete and the budget is
+    released."""
+    S = P_serving()
+    reqs, geoms = _requests(P, count=3, seed=33)
+    bad_ev = reqs[0].events.copy()
+    bad_ev[5, 0] = 30000
+    bad = S.Request(reqs[0].geom, bad_ev, reqs[0].s, reqs[0].x0, n_subsets=8, epochs=1, name="bad")
+    with S.Server(hbm_budget=8 << 30, max_active=2) as srv:
+        for g in geoms:
+            srv.warm(g)
+        fb = srv.submit(bad)
+        futs = [srv.submit(r) for r in reqs]
+        res = [f.result(timeout=120) for f in futs]
+        with pytest.raises(P.LMError):
+            fb.result(timeout=120)
+    assert [r.name for r in res] == [r.name for r in reqs]
+    assert srv._used == 0
