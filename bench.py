@@ -15,7 +15,8 @@ region.
 It prints one JSON line: value = events forward- and back-projected per
 second over the timed epochs, the roofline of the dominant kernel, the FP64
 oracle timed on a bounded sample of the same workload on the host
-(cpu_baseline) and, unless --no-serve, the serving measurement: 64
+(cpu_baseline), seconds per epoch of the 2D workload (1e5 events, 128x128,
+28 subsets) and, unless --no-serve, the serving measurement: 64
 dynamic-frame requests (event counts log-uniform in 1e5..5e7, half on a
 128x128x48 grid and half on the 200x200x96 one, 28 subsets, 3 epochs each)
 arriving as a Poisson stream at 0.7 of the sequential solver's throughput,
@@ -119,7 +120,7 @@ def roofline(cls: str, bytes_per_launch: float, us_per_launch: float) -> dict:
             "sources": source_digest(cls)}
 
 
-def cpu_baseline(p, g, n_sample_subsets: int = 3):
+def cpu_baseline(p, g, n_sample_subsets: int = 12):
     """The FP64 oracle on a bounded sample of the workload: the events of a
     few data subsets (the sample problem) are initialised untimed, then as
     many data updates and prior updates are timed and scaled to one epoch."""
@@ -297,6 +298,38 @@ def epoch_leg(args, torch, P, lmsynth):
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create": round(t_plan, 3)},
     }
     return out, p, G, g
+
+
+# --------------------------------------------------------------------------- 2D
+
+
+def leg_2d(torch, P, lmsynth, epochs: int = 10):
+    """LM-SPDHG seconds per epoch on the 2D workload (360 crystals, 128x128
+    image, 1e5 events, 28 subsets, TV beta 0.03): 10 epochs after one
+    warm-up epoch, on the plan's stream."""
+    dev = torch.device("cuda", 0)
+    p = lmsynth.simulate_2d(lmsynth.config_2d())
+    G = P.Geometry.from_problem(p, device=dev)
+    ev = G.events(p.events)
+    s = torch.as_tensor(p.s, device=dev)
+    g = P.lm_sens(G)
+    gamma = float(np.float32(3.0 / float(p.x0.max())))
+    n = 28
+    plan = P.Plan(G, ev, s, n, gamma, RHO, BETA, g=g)
+    x = torch.as_tensor(p.x0, device=dev).clone()
+    plan.init(x)
+    seqs = [lmsynth.subset_sequence(2000, k * 2 * n, 2 * n, n) for k in range(epochs + 1)]
+    plan.epoch(x, seqs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, epochs + 1):
+        plan.epoch(x, seqs[k])
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / epochs
+    plan.destroy()
+    log(f"2D workload: {1e3 * t:.2f} ms per epoch ({2 * n} updates)")
+    return {"workload": "2d_360_128x128: 1e5 TOF events, 28 subsets, TV beta 0.03", "epochs": epochs,
+            "s_per_epoch": round(t, 6), "us_per_update": round(1e6 * t / (2 * n), 2)}
 
 
 # --------------------------------------------------------------------------- serving
@@ -507,6 +540,7 @@ def main() -> int:
             log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
     else:
         out, p, G, g = epoch_leg(args, torch, P, lmsynth)
+        out["epoch_2d"] = leg_2d(torch, P, lmsynth)
         if not args.no_serve:
             out["served"] = serving_leg(torch, P, lmsynth, G, g, p)
         cpu = None
