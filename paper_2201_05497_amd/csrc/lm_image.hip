@@ -243,6 +243,215 @@ __global__ __launch_bounds__(kBlock) void k_tv_tiled(const float *__restrict__ x
     zbar[p] = zb;
 }
 
+// Index of voxel (i, j, k) in the 4x4x4 brick layout with nbx x nby bricks
+// per brick layer, split into a part that depends on (i, j) and one that
+// depends on k only.
+__device__ __forceinline__ int brick_ij(int nbx, int i, int j) {
+  return (((j >> 2) * nbx + (i >> 2)) << 6) | ((j & 3) << 2) | (i & 3);
+}
+__device__ __forceinline__ int brick_k(int nbx, int nby, int k) { return (((k >> 2) * nby * nbx) << 6) | ((k & 3) << 4); }
+
+// The whole prior update for a 3D image in the 4x4x4 brick layout, marching
+// along z.  A block owns a column of 16 x 16 voxels and a run of CZ planes
+// (plus one plane below it, whose dual step only feeds the z-difference of
+// the first plane).  Per plane k it holds x of planes k and k+1 with a
+// one-voxel ring in LDS (two 18 x 18 buffers) and x of plane k+2 in
+// registers, computes
+// q = proj_beta(w + S K x) - w for its 256 voxels and for the 32 voxels of
+// the lower x- and y-faces of the ring (K^T q needs q at the three lower
+// neighbours; the z one is the same thread's q of plane k-1), writes w+,
+// then dz = K^T q, z, zbar and the fused primal step.  The loads of later
+// planes (x three planes ahead, w, z and T one plane ahead) are issued
+// before the current plane is computed.  Thread t owns
+// voxel (t & 3) + 4 (t >> 4 & 3), ((t >> 2) & 3) + 4 (t >> 6) of the column,
+// so a wavefront reads four 64-byte brick slabs per plane.  Columns are
+// dealt so that each XCD works on a contiguous run (halo reads stay in its
+// L2).  x and w are read-only; results go to x_out and w_out.
+template <int CZ>
+__global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x, const float *__restrict__ w,
+                                                     float *__restrict__ w_out, float *__restrict__ z,
+                                                     float *__restrict__ x_out, const float *__restrict__ T,
+                                                     float *__restrict__ zbar, int nbx, int nby, int nx, int ny,
+                                                     int nz, long long ne, float Sp, float beta, float inv_p,
+                                                     int fuse, int nblocks) {
+  constexpr int B = 18;   // x box: x0-1 .. x0+16
+  constexpr int Q = 17;   // q box: x0-1 .. x0+15
+  __shared__ float xb[2][B * B];
+  __shared__ float q0s[Q * Q], q1s[Q * Q];
+  int blk = blockIdx.x;
+  const int full = nblocks & ~7;
+  if (blk < full) blk = (blk & 7) * (full >> 3) + (blk >> 3);
+  const int ntx = (nx + 15) >> 4, nty = (ny + 15) >> 4;
+  const int cx = blk % ntx, cy = (blk / ntx) % nty, cz = blk / (ntx * nty);
+  const int x0 = cx * 16, y0 = cy * 16;
+  const int kz0 = cz * CZ, kz1 = min(nz, kz0 + CZ);
+  const int ks = kz0 > 0 ? kz0 - 1 : 0;
+  const int t = threadIdx.x;
+  // own voxel
+  const int ti = (t & 3) + 4 * ((t >> 4) & 3), tj = ((t >> 2) & 3) + 4 * (t >> 6);
+  const int i = x0 + ti, j = y0 + tj;
+  const bool own = i < nx && j < ny;
+  const int own_b = (ti + 1) + B * (tj + 1), own_q = (ti + 1) + Q * (tj + 1);
+  const int own_ij = own ? brick_ij(nbx, i, j) : 0;
+  // ring of the x box (68 positions): rows by = 0 and 17, columns bx = 0 and 17
+  int rb = -1, r_ij = 0;
+  bool r_ok = false;
+  if (t < 68) {
+    int bx, by;
+    if (t < 18) { bx = t; by = 0; }
+    else if (t < 36) { bx = t - 18; by = 17; }
+    else if (t < 52) { bx = 0; by = t - 35; }
+    else { bx = 17; by = t - 51; }
+    rb = bx + B * by;
+    const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
+    r_ok = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+    r_ij = r_ok ? brick_ij(nbx, gi, gj) : 0;
+  }
+  // q on the lower faces: t < 16: (x0-1, y0+t); 16 <= t < 32: (x0+t-16, y0-1)
+  int hb = 0, hq = 0, h_ij = 0, hgi = 0, hgj = 0;
+  bool h_ok = false;
+  if (t < 32) {
+    const int bx = t < 16 ? 0 : t - 15, by = t < 16 ? t + 1 : 0;
+    hb = bx + B * by;
+    hq = bx + Q * by;
+    hgi = x0 - 1 + bx;
+    hgj = y0 - 1 + by;
+    h_ok = hgi >= 0 && hgi < nx && hgj >= 0 && hgj < ny;
+    h_ij = h_ok ? brick_ij(nbx, hgi, hgj) : 0;
+  }
+  auto load_x = [&](int k, float &xo, float &xr) {
+    xo = 0.0f;
+    xr = 0.0f;
+    if (k < nz) {
+      const int off = brick_k(nbx, nby, k);
+      if (own) xo = x[own_ij + off];
+      if (r_ok) xr = x[r_ij + off];
+    }
+  };
+  auto load_w = [&](int k, float (&wo)[3], float (&wh)[3], float &zo, float &to) {
+    const int off = brick_k(nbx, nby, k);
+    wo[0] = wo[1] = wo[2] = wh[0] = wh[1] = wh[2] = zo = to = 0.0f;
+    if (own) {
+      wo[0] = w[own_ij + off];
+      wo[1] = w[ne + own_ij + off];
+      wo[2] = w[2 * ne + own_ij + off];
+      if (k >= kz0) {
+        zo = z[own_ij + off];
+        if (fuse) to = T[own_ij + off];
+      }
+    }
+    if (h_ok && k >= kz0) {
+      wh[0] = w[h_ij + off];
+      wh[1] = w[ne + h_ij + off];
+      wh[2] = w[2 * ne + h_ij + off];
+    }
+  };
+  auto prox = [&](float gx, float gy, float gz, const float (&wv)[3], float (&q)[3]) {
+    const float v0 = fmaf(Sp, gx, wv[0]), v1 = fmaf(Sp, gy, wv[1]), v2 = fmaf(Sp, gz, wv[2]);
+    const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
+    const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
+    q[0] = v0 * sc - wv[0];
+    q[1] = v1 * sc - wv[1];
+    q[2] = v2 * sc - wv[2];
+  };
+  // planes ks and ks+1 into LDS, plane ks+2 into registers (x is read two
+  // planes ahead, so a load has a whole plane step to arrive); w, z, T of
+  // plane ks into registers
+  float pxo, pxr;
+  {
+    float a, b, c, d;
+    load_x(ks, a, b);
+    load_x(ks + 1, c, d);
+    load_x(ks + 2, pxo, pxr);
+    xb[0][own_b] = a;
+    xb[1][own_b] = c;
+    if (rb >= 0) {
+      xb[0][rb] = b;
+      xb[1][rb] = d;
+    }
+  }
+  float wo[3], wh[3], zo, to;
+  load_w(ks, wo, wh, zo, to);
+  float q2prev = 0.0f;
+  int cur = 0;
+  __syncthreads();
+  for (int k = ks; k < kz1; ++k) {
+    // next loads: x of plane k+3, w / z / T of plane k+1
+    float nxo, nxr, nwo[3], nwh[3], nzo, nto;
+    load_x(k + 3, nxo, nxr);
+    if (k + 1 < kz1) load_w(k + 1, nwo, nwh, nzo, nto);
+    const float *xc = xb[cur], *xn = xb[cur ^ 1];
+    const bool out = k >= kz0;
+    // q of the own voxel
+    const float xv = xc[own_b];
+    float q[3];
+    {
+      const float gx = (i < nx - 1) ? xc[own_b + 1] - xv : 0.0f;
+      const float gy = (j < ny - 1) ? xc[own_b + B] - xv : 0.0f;
+      const float gz = (k < nz - 1) ? xn[own_b] - xv : 0.0f;
+      prox(gx, gy, gz, wo, q);
+    }
+    if (out && own) {
+      const int p = own_ij + brick_k(nbx, nby, k);
+      w_out[p] = wo[0] + q[0];
+      w_out[ne + p] = wo[1] + q[1];
+      w_out[2 * ne + p] = wo[2] + q[2];
+    }
+    q0s[own_q] = q[0];
+    q1s[own_q] = q[1];
+    // q on the lower faces (only the component the own voxels need)
+    if (t < 32 && out) {
+      float hqv[3] = {0.0f, 0.0f, 0.0f};
+      if (h_ok) {
+        const float hv = xc[hb];
+        const float gx = (hgi < nx - 1) ? xc[hb + 1] - hv : 0.0f;
+        const float gy = (hgj < ny - 1) ? xc[hb + B] - hv : 0.0f;
+        const float gz = (k < nz - 1) ? xn[hb] - hv : 0.0f;
+        prox(gx, gy, gz, wh, hqv);
+      }
+      if (t < 16)
+        q0s[hq] = hqv[0];
+      else
+        q1s[hq] = hqv[1];
+    }
+    __syncthreads();
+    // plane k+2 (loaded one step ago) replaces plane k in LDS (nobody reads
+    // plane k any more)
+    xb[cur][own_b] = pxo;
+    if (rb >= 0) xb[cur][rb] = pxr;
+    pxo = nxo;
+    pxr = nxr;
+    if (out && own) {
+      float dz = 0.0f;
+      if (i < nx - 1) dz -= q0s[own_q];
+      if (i > 0) dz += q0s[own_q - 1];
+      if (j < ny - 1) dz -= q1s[own_q];
+      if (j > 0) dz += q1s[own_q - Q];
+      if (k < nz - 1) dz -= q[2];
+      if (k > 0) dz += q2prev;
+      const int p = own_ij + brick_k(nbx, nby, k);
+      const float zn = zo + dz;
+      const float zb = fmaf(dz, inv_p, zn);
+      z[p] = zn;
+      if (fuse)
+        x_out[p] = fmaxf(0.0f, fmaf(-to, zb, xv));
+      else
+        zbar[p] = zb;
+    }
+    q2prev = q[2];
+    if (k + 1 < kz1) {
+      for (int c = 0; c < 3; ++c) {
+        wo[c] = nwo[c];
+        wh[c] = nwh[c];
+      }
+      zo = nzo;
+      to = nto;
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+}
+
 // Row-major image (caller layout) -> layout L, ncomp components; padding is
 // left untouched (zero).
 __global__ __launch_bounds__(kBlock) void k_to_layout(const float *__restrict__ src, float *__restrict__ dst,
@@ -327,7 +536,12 @@ int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, 
                     float *z, float *x_out, const float *T, float *zbar, float Sp, float beta, float inv_p, bool fuse,
                     hipStream_t st) {
   const long long ne = layout_size(L);
-  if (L.sx == 2 && L.sy == 2 && L.sz == 2) {
+  if (L.sx == 2 && L.sy == 2 && L.sz == 2 && ncomp == 3) {
+    constexpr int CZ = 4;
+    const int nblocks = ((n[0] + 15) / 16) * ((n[1] + 15) / 16) * ((n[2] + CZ - 1) / CZ);
+    hipLaunchKernelGGL((k_tv_march<CZ>), dim3(nblocks), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar, L.nbx,
+                       L.nby, n[0], n[1], n[2], ne, Sp, beta, inv_p, fuse ? 1 : 0, nblocks);
+  } else if (L.sx == 2 && L.sy == 2 && L.sz == 2) {
     const int ntiles = ((L.nbx + 1) / 2) * ((L.nby + 1) / 2) * L.nbz;
     hipLaunchKernelGGL((k_tv_tiled<4, 4, 4, 2, 2>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar,
                        L, n[0], n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0, ntiles);

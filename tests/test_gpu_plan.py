@@ -331,3 +331,46 @@ def test_kernel_timing_sampling(P):
         assert counts[3][k] == (c + 2) // 3, (k, c, counts[3][k])
     # atomics make runs differ in the last bits only
     assert img_err(xs[1], xs[0]) <= 1e-5 and img_err(xs[2], xs[0]) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 11), (16, 16, 4), (20, 33, 9), (5, 7, 2)])
+def test_prior_updates_ragged_grids(P, shape):
+    """Prior updates alone from a random state on 3D grids whose sizes are not
+    multiples of the kernels' column (16 x 16) and chunk (4 planes) sizes,
+    against the oracle: x and z in sup-norm, w in relative L2 (its sup-norm
+    follows the float32 error of K x on the beta-sphere)."""
+    nx, ny, nz = shape
+    sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
+    tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
+    img = lmsynth.ImageGeom((nx, ny, nz), (3.0, 2.5, 3.5))
+    p = lmsynth.simulate_3d(lmsynth.Problem("ragged", sc, img, tof, 4, 1, 0.03), n_prompts=5000, seed=77,
+                            workers=1)
+    n, beta = 4, 0.03
+    rng = np.random.default_rng(sum(shape))
+    zyx = (nz, ny, nx)
+    g = (5.0 + rng.uniform(0.0, 1.0, zyx)).astype(np.float32)
+    x_start = rng.uniform(0.5, 1.5, zyx).astype(np.float32)
+    z0 = rng.uniform(-0.5, 0.5, zyx).astype(np.float32)
+    zb0 = rng.uniform(-0.5, 0.5, zyx).astype(np.float32)
+    w0 = rng.normal(0.0, beta / 3, (3,) + zyx).astype(np.float32)
+    w0 *= np.minimum(1.0, beta / np.maximum(np.sqrt((w0.astype(np.float64) ** 2).sum(0)), 1e-30)).astype(np.float32)
+    c0 = rng.uniform(0.1, 0.9, len(p.events)).astype(np.float32)
+    Go = oracle.Geometry.from_problem(p)
+    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO)
+    st0 = oracle.LMState(x=x_start.astype(np.float64), z=z0.astype(np.float64), zbar=zb0.astype(np.float64),
+                         w=w0.astype(np.float64), y=1.0 - c0.astype(np.float64), u=0)
+    seq = np.full(6, n, dtype=np.int32)
+    x_o, st, _ = oracle.lm_spdhg(Go, p.events, p.s.astype(np.float64), g.astype(np.float64), x_start, n, seq,
+                                 _gamma(p.x0), RHO, beta, setup=su, state=st0)
+    Gg, plan = _plan(P, p, n, g, beta)
+    cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+    plan.set_state({"z": cuda(z0), "zbar": cuda(zb0), "w": cuda(w0), "c": cuda(c0), "u": 0})
+    x = cuda(x_start)
+    plan.epoch(x, seq)
+    state = plan.get_state()
+    ex = img_err(x.cpu().numpy(), x_o)
+    ez = img_err(state["z"].cpu().numpy(), st.z)
+    wg = state["w"].cpu().numpy().astype(np.float64)
+    ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
+    report(f"prior updates {shape}", x_err=ex, z_err=ez, w_l2=ew)
+    assert ex <= ITER_TOL and ez <= ITER_TOL and ew <= ITER_TOL
