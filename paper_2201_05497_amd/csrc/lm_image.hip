@@ -115,18 +115,18 @@ __global__ __launch_bounds__(kBlock) void k_tv_fused(const float *__restrict__ x
     zbar[p] = zb;
 }
 
-// The whole prior update, tiled through LDS.  A block owns a tile of
-// TBX x TBY x 1 bricks (2 x 2 bricks of 4x4x4 voxels, or 4 x 4 bricks of
-// 4x4x1 for a single slice: 256 voxels); wavefront w reads brick w of the
-// tile, so those loads are whole 256-byte bricks.  The tile stages x with a
-// one-voxel halo and computes q = proj_beta(w + S K x) - w once for the tile
-// and its lower halo (K^T q at a voxel needs q at the voxel and at its three
-// lower neighbours), then forms dz = K^T q, z, zbar and the fused primal
-// step.  Every global load of the block is issued before the first barrier.
-// Tiles are numbered so that each XCD (blocks are dealt to the 8 XCDs round
-// robin) works on one contiguous run of tiles, which keeps the halo reads of
-// neighbouring tiles in that XCD's L2.  x and w are read-only; results go to
-// x_out and w_out.
+// The whole prior update, tiled through LDS (used for single-slice images;
+// 3D images take the z-marching kernel below).  A block owns a tile of
+// TBX x TBY x 1 bricks (4 x 4 bricks of 4x4x1 voxels: 256 voxels);
+// wavefront w reads brick w of the tile, so those loads are whole bricks.
+// The tile stages x with a one-voxel halo and computes
+// q = proj_beta(w + S K x) - w once for the tile and its lower halo (K^T q at
+// a voxel needs q at the voxel and at its lower neighbours), then forms
+// dz = K^T q, z, zbar and the fused primal step.  Every global load of the
+// block is issued before the first barrier.  Tiles are numbered so that
+// each XCD (blocks are dealt to the 8 XCDs round robin) works on one
+// contiguous run of tiles, which keeps the halo reads of neighbouring tiles
+// in that XCD's L2.  x and w are read-only; results go to x_out and w_out.
 template <int BX, int BY, int BZ, int TBX, int TBY>
 __global__ __launch_bounds__(kBlock) void k_tv_tiled(const float *__restrict__ x, const float *__restrict__ w,
                                                      float *__restrict__ w_out, float *__restrict__ z,
@@ -243,41 +243,41 @@ __global__ __launch_bounds__(kBlock) void k_tv_tiled(const float *__restrict__ x
     zbar[p] = zb;
 }
 
-// Index of voxel (i, j, k) in the 4x4x4 brick layout with nbx x nby bricks
-// per brick layer, split into a part that depends on (i, j) and one that
-// depends on k only.
+// The part of the index of voxel (i, j, k) in the 4x4x4 brick layout (nbx
+// bricks along x) that depends on (i, j); the k part is added per plane.
 __device__ __forceinline__ int brick_ij(int nbx, int i, int j) {
   return (((j >> 2) * nbx + (i >> 2)) << 6) | ((j & 3) << 2) | (i & 3);
 }
-__device__ __forceinline__ int brick_k(int nbx, int nby, int k) { return (((k >> 2) * nby * nbx) << 6) | ((k & 3) << 4); }
 
 // The whole prior update for a 3D image in the 4x4x4 brick layout, marching
-// along z.  A block owns a column of 16 x 16 voxels and a run of CZ planes
-// (plus one plane below it, whose dual step only feeds the z-difference of
-// the first plane).  Per plane k it holds x of planes k and k+1 with a
-// one-voxel ring in LDS (two 18 x 18 buffers) and x of plane k+2 in
-// registers, computes
-// q = proj_beta(w + S K x) - w for its 256 voxels and for the 32 voxels of
-// the lower x- and y-faces of the ring (K^T q needs q at the three lower
-// neighbours; the z one is the same thread's q of plane k-1), writes w+,
-// then dz = K^T q, z, zbar and the fused primal step.  The loads of later
-// planes (x three planes ahead, w, z and T one plane ahead) are issued
-// before the current plane is computed.  Thread t owns
-// voxel (t & 3) + 4 (t >> 4 & 3), ((t >> 2) & 3) + 4 (t >> 6) of the column,
-// so a wavefront reads four 64-byte brick slabs per plane.  Columns are
-// dealt so that each XCD works on a contiguous run (halo reads stay in its
-// L2).  x and w are read-only; results go to x_out and w_out.
+// along z two planes per step.  A block owns a 16 x 16 column and a run of
+// CZ planes (CZ even, so a step covers planes k and k+1 of one brick layer
+// and writes whole 128-byte lines of every brick).  Thread t owns voxel
+// (t & 3) + 4 (t >> 4 & 3), ((t >> 2) & 3) + 4 (t >> 6) of the column in
+// every plane, so a wavefront reads four 64-byte brick slabs per plane; K^T q
+// needs q at the three lower neighbours, which are the thread's own q of the
+// plane below (z), LDS (x, y) or the lower faces of the column's ring.
+// Columns are dealt so that each XCD works on a contiguous run (halo reads
+// stay in its L2).  x and w are read-only; results go to x_out and w_out.  The
+// dual step of the plane below the run is computed first (own voxels only);
+// it feeds the z-difference of the run's first plane.  Per step the block
+// holds x of planes k, k+1, k+2 with a one-voxel ring in LDS (three 18 x 18
+// buffers, used as a ring) and x of planes k+3, k+4 in registers (loaded one
+// step ahead); w, z and T of the next two planes are loaded one step ahead.
+// Threads 0..31 compute the lower-face dual steps of plane k, threads
+// 32..63 those of plane k+1; threads 0..135 load the x ring of two planes.
 template <int CZ>
 __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x, const float *__restrict__ w,
-                                                     float *__restrict__ w_out, float *__restrict__ z,
-                                                     float *__restrict__ x_out, const float *__restrict__ T,
-                                                     float *__restrict__ zbar, int nbx, int nby, int nx, int ny,
-                                                     int nz, long long ne, float Sp, float beta, float inv_p,
-                                                     int fuse, int nblocks) {
-  constexpr int B = 18;   // x box: x0-1 .. x0+16
-  constexpr int Q = 17;   // q box: x0-1 .. x0+15
-  __shared__ float xb[2][B * B];
-  __shared__ float q0s[Q * Q], q1s[Q * Q];
+                                                      float *__restrict__ w_out, float *__restrict__ z,
+                                                      float *__restrict__ x_out, const float *__restrict__ T,
+                                                      float *__restrict__ zbar, int nbx, int nby, int nx, int ny,
+                                                      int nz, long long ne, float Sp, float beta, float inv_p,
+                                                      int fuse, int nblocks) {
+  static_assert(CZ % 2 == 0, "two planes per step");
+  constexpr int B = 18;  // x box: x0-1 .. x0+16
+  constexpr int Q = 17;  // q box: x0-1 .. x0+15
+  __shared__ float xb[3][B * B];
+  __shared__ float q0s[2][Q * Q], q1s[2][Q * Q];
   int blk = blockIdx.x;
   const int full = nblocks & ~7;
   if (blk < full) blk = (blk & 7) * (full >> 3) + (blk >> 3);
@@ -285,33 +285,36 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
   const int cx = blk % ntx, cy = (blk / ntx) % nty, cz = blk / (ntx * nty);
   const int x0 = cx * 16, y0 = cy * 16;
   const int kz0 = cz * CZ, kz1 = min(nz, kz0 + CZ);
-  const int ks = kz0 > 0 ? kz0 - 1 : 0;
   const int t = threadIdx.x;
-  // own voxel
+  // own voxel (one per thread in every plane)
   const int ti = (t & 3) + 4 * ((t >> 4) & 3), tj = ((t >> 2) & 3) + 4 * (t >> 6);
   const int i = x0 + ti, j = y0 + tj;
   const bool own = i < nx && j < ny;
   const int own_b = (ti + 1) + B * (tj + 1), own_q = (ti + 1) + Q * (tj + 1);
   const int own_ij = own ? brick_ij(nbx, i, j) : 0;
-  // ring of the x box (68 positions): rows by = 0 and 17, columns bx = 0 and 17
-  int rb = -1, r_ij = 0;
+  // ring of the x box: threads 0..67 plane a, 68..135 plane a+1 of a pair
+  int rb = -1, r_ij = 0, rpl = 0;
   bool r_ok = false;
-  if (t < 68) {
+  if (t < 136) {
+    const int r = t < 68 ? t : t - 68;
+    rpl = t < 68 ? 0 : 1;
     int bx, by;
-    if (t < 18) { bx = t; by = 0; }
-    else if (t < 36) { bx = t - 18; by = 17; }
-    else if (t < 52) { bx = 0; by = t - 35; }
-    else { bx = 17; by = t - 51; }
+    if (r < 18) { bx = r; by = 0; }
+    else if (r < 36) { bx = r - 18; by = 17; }
+    else if (r < 52) { bx = 0; by = r - 35; }
+    else { bx = 17; by = r - 51; }
     rb = bx + B * by;
     const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
     r_ok = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
     r_ij = r_ok ? brick_ij(nbx, gi, gj) : 0;
   }
-  // q on the lower faces: t < 16: (x0-1, y0+t); 16 <= t < 32: (x0+t-16, y0-1)
-  int hb = 0, hq = 0, h_ij = 0, hgi = 0, hgj = 0;
+  // lower-face dual steps: threads 0..31 plane k, 32..63 plane k+1
+  int hb = 0, hq = 0, h_ij = 0, hgi = 0, hgj = 0, hpl = 0;
   bool h_ok = false;
-  if (t < 32) {
-    const int bx = t < 16 ? 0 : t - 15, by = t < 16 ? t + 1 : 0;
+  if (t < 64) {
+    const int u = t & 31;
+    hpl = t >> 5;
+    const int bx = u < 16 ? 0 : u - 15, by = u < 16 ? u + 1 : 0;
     hb = bx + B * by;
     hq = bx + Q * by;
     hgi = x0 - 1 + bx;
@@ -319,135 +322,168 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
     h_ok = hgi >= 0 && hgi < nx && hgj >= 0 && hgj < ny;
     h_ij = h_ok ? brick_ij(nbx, hgi, hgj) : 0;
   }
-  auto load_x = [&](int k, float &xo, float &xr) {
-    xo = 0.0f;
-    xr = 0.0f;
-    if (k < nz) {
-      const int off = brick_k(nbx, nby, k);
-      if (own) xo = x[own_ij + off];
-      if (r_ok) xr = x[r_ij + off];
-    }
-  };
-  auto load_w = [&](int k, float (&wo)[3], float (&wh)[3], float &zo, float &to) {
-    const int off = brick_k(nbx, nby, k);
-    wo[0] = wo[1] = wo[2] = wh[0] = wh[1] = wh[2] = zo = to = 0.0f;
-    if (own) {
-      wo[0] = w[own_ij + off];
-      wo[1] = w[ne + own_ij + off];
-      wo[2] = w[2 * ne + own_ij + off];
-      if (k >= kz0) {
-        zo = z[own_ij + off];
-        if (fuse) to = T[own_ij + off];
-      }
-    }
-    if (h_ok && k >= kz0) {
-      wh[0] = w[h_ij + off];
-      wh[1] = w[ne + h_ij + off];
-      wh[2] = w[2 * ne + h_ij + off];
-    }
-  };
-  auto prox = [&](float gx, float gy, float gz, const float (&wv)[3], float (&q)[3]) {
-    const float v0 = fmaf(Sp, gx, wv[0]), v1 = fmaf(Sp, gy, wv[1]), v2 = fmaf(Sp, gz, wv[2]);
+  const int koff_layer = (nby * nbx) << 6;
+  auto koff = [&](int k) { return (k >> 2) * koff_layer + ((k & 3) << 4); };
+  // x of the own voxel of plane k and of this thread's ring position of
+  // plane k + rpl (0 where outside the image)
+  auto load_own = [&](int k) { return (own && k < nz) ? x[own_ij + koff(k)] : 0.0f; };
+  auto load_ring = [&](int k) { return (r_ok && k + rpl < nz) ? x[r_ij + koff(k + rpl)] : 0.0f; };
+  auto prox = [&](float gx, float gy, float gz, float w0, float w1, float w2, float &q0, float &q1, float &q2) {
+    const float v0 = fmaf(Sp, gx, w0), v1 = fmaf(Sp, gy, w1), v2 = fmaf(Sp, gz, w2);
     const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
     const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
-    q[0] = v0 * sc - wv[0];
-    q[1] = v1 * sc - wv[1];
-    q[2] = v2 * sc - wv[2];
+    q0 = v0 * sc - w0;
+    q1 = v1 * sc - w1;
+    q2 = v2 * sc - w2;
   };
-  // planes ks and ks+1 into LDS, plane ks+2 into registers (x is read two
-  // planes ahead, so a load has a whole plane step to arrive); w, z, T of
-  // plane ks into registers
-  float pxo, pxr;
-  {
-    float a, b, c, d;
-    load_x(ks, a, b);
-    load_x(ks + 1, c, d);
-    load_x(ks + 2, pxo, pxr);
-    xb[0][own_b] = a;
-    xb[1][own_b] = c;
-    if (rb >= 0) {
-      xb[0][rb] = b;
-      xb[1][rb] = d;
-    }
-  }
-  float wo[3], wh[3], zo, to;
-  load_w(ks, wo, wh, zo, to);
+  // dual step of the plane below the run, own voxels only (its z-component
+  // feeds the first plane's z-difference)
   float q2prev = 0.0f;
-  int cur = 0;
-  __syncthreads();
-  for (int k = ks; k < kz1; ++k) {
-    // next loads: x of plane k+3, w / z / T of plane k+1
-    float nxo, nxr, nwo[3], nwh[3], nzo, nto;
-    load_x(k + 3, nxo, nxr);
-    if (k + 1 < kz1) load_w(k + 1, nwo, nwh, nzo, nto);
-    const float *xc = xb[cur], *xn = xb[cur ^ 1];
-    const bool out = k >= kz0;
-    // q of the own voxel
-    const float xv = xc[own_b];
-    float q[3];
-    {
-      const float gx = (i < nx - 1) ? xc[own_b + 1] - xv : 0.0f;
-      const float gy = (j < ny - 1) ? xc[own_b + B] - xv : 0.0f;
-      const float gz = (k < nz - 1) ? xn[own_b] - xv : 0.0f;
-      prox(gx, gy, gz, wo, q);
-    }
-    if (out && own) {
-      const int p = own_ij + brick_k(nbx, nby, k);
-      w_out[p] = wo[0] + q[0];
-      w_out[ne + p] = wo[1] + q[1];
-      w_out[2 * ne + p] = wo[2] + q[2];
-    }
-    q0s[own_q] = q[0];
-    q1s[own_q] = q[1];
-    // q on the lower faces (only the component the own voxels need)
-    if (t < 32 && out) {
-      float hqv[3] = {0.0f, 0.0f, 0.0f};
-      if (h_ok) {
-        const float hv = xc[hb];
-        const float gx = (hgi < nx - 1) ? xc[hb + 1] - hv : 0.0f;
-        const float gy = (hgj < ny - 1) ? xc[hb + B] - hv : 0.0f;
-        const float gz = (k < nz - 1) ? xn[hb] - hv : 0.0f;
-        prox(gx, gy, gz, wh, hqv);
-      }
-      if (t < 16)
-        q0s[hq] = hqv[0];
-      else
-        q1s[hq] = hqv[1];
+  if (kz0 > 0) {
+    const int kb = kz0 - 1;
+    // planes kb (own + ring) and kz0 (own) through LDS buffers 0 and 1
+    xb[0][own_b] = load_own(kb);
+    if (rb >= 0 && rpl == 0) xb[0][rb] = load_ring(kb);
+    const float xup = load_own(kz0);
+    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+    if (own) {
+      const int p = own_ij + koff(kb);
+      w0 = w[p];
+      w1 = w[ne + p];
+      w2 = w[2 * ne + p];
     }
     __syncthreads();
-    // plane k+2 (loaded one step ago) replaces plane k in LDS (nobody reads
-    // plane k any more)
-    xb[cur][own_b] = pxo;
-    if (rb >= 0) xb[cur][rb] = pxr;
-    pxo = nxo;
-    pxr = nxr;
-    if (out && own) {
-      float dz = 0.0f;
-      if (i < nx - 1) dz -= q0s[own_q];
-      if (i > 0) dz += q0s[own_q - 1];
-      if (j < ny - 1) dz -= q1s[own_q];
-      if (j > 0) dz += q1s[own_q - Q];
-      if (k < nz - 1) dz -= q[2];
-      if (k > 0) dz += q2prev;
-      const int p = own_ij + brick_k(nbx, nby, k);
-      const float zn = zo + dz;
-      const float zb = fmaf(dz, inv_p, zn);
-      z[p] = zn;
-      if (fuse)
-        x_out[p] = fmaxf(0.0f, fmaf(-to, zb, xv));
-      else
-        zbar[p] = zb;
+    const float xv = xb[0][own_b];
+    const float gx = (i < nx - 1) ? xb[0][own_b + 1] - xv : 0.0f;
+    const float gy = (j < ny - 1) ? xb[0][own_b + B] - xv : 0.0f;
+    const float gz = xup - xv;  // kb < nz - 1
+    float q0, q1;
+    prox(gx, gy, gz, w0, w1, w2, q0, q1, q2prev);
+    __syncthreads();
+  }
+  // planes kz0, kz0+1, kz0+2 into LDS; kz0+3, kz0+4 into registers
+  int bk0 = 0, bk1 = 1, bk2 = 2;  // LDS buffers of planes k, k+1, k+2
+  xb[0][own_b] = load_own(kz0);
+  xb[1][own_b] = load_own(kz0 + 1);
+  xb[2][own_b] = load_own(kz0 + 2);
+  if (rb >= 0) {
+    // ring threads of plane a load planes a = kz0 and kz0+2; those of
+    // plane a+1 load kz0+1
+    if (rpl == 0) {
+      xb[0][rb] = load_ring(kz0);
+      xb[2][rb] = load_ring(kz0 + 2);
+    } else {
+      xb[1][rb] = load_ring(kz0);
     }
-    q2prev = q[2];
-    if (k + 1 < kz1) {
-      for (int c = 0; c < 3; ++c) {
-        wo[c] = nwo[c];
-        wh[c] = nwh[c];
+  }
+  float pxo0 = load_own(kz0 + 3), pxo1 = load_own(kz0 + 4), pxr = load_ring(kz0 + 3);
+  // w, z, T of the own voxel for planes k, k+1; w of the face voxel
+  float wo[2][3], zo[2], to[2], wh[3];
+  auto load_w = [&](int k, float (&wv)[2][3], float (&zv)[2], float (&tv)[2], float (&whv)[3]) {
+    for (int s = 0; s < 2; ++s) {
+      wv[s][0] = wv[s][1] = wv[s][2] = zv[s] = tv[s] = 0.0f;
+      if (own && k + s < kz1) {
+        const int p = own_ij + koff(k + s);
+        wv[s][0] = w[p];
+        wv[s][1] = w[ne + p];
+        wv[s][2] = w[2 * ne + p];
+        zv[s] = z[p];
+        if (fuse) tv[s] = T[p];
       }
-      zo = nzo;
-      to = nto;
     }
-    cur ^= 1;
+    whv[0] = whv[1] = whv[2] = 0.0f;
+    if (h_ok && k + hpl < kz1) {
+      const int p = h_ij + koff(k + hpl);
+      whv[0] = w[p];
+      whv[1] = w[ne + p];
+      whv[2] = w[2 * ne + p];
+    }
+  };
+  load_w(kz0, wo, zo, to, wh);
+  __syncthreads();
+  for (int k = kz0; k < kz1; k += 2) {
+    // loads for the next step: x of planes k+5, k+6; w, z, T of k+2, k+3
+    const float nxo0 = load_own(k + 5), nxo1 = load_own(k + 6), nxr = load_ring(k + 5);
+    float nwo[2][3], nzo[2], nto[2], nwh[3];
+    load_w(k + 2, nwo, nzo, nto, nwh);
+    const float *xa = xb[bk0], *xc = xb[bk1], *xd = xb[bk2];
+    // own dual steps of planes k (s = 0) and k+1 (s = 1)
+    float q[2][3], xv[2];
+    for (int s = 0; s < 2; ++s) {
+      const float *xs = s ? xc : xa, *xu = s ? xd : xc;
+      const int kk = k + s;
+      xv[s] = xs[own_b];
+      const float gx = (i < nx - 1) ? xs[own_b + 1] - xv[s] : 0.0f;
+      const float gy = (j < ny - 1) ? xs[own_b + B] - xv[s] : 0.0f;
+      const float gz = (kk < nz - 1) ? xu[own_b] - xv[s] : 0.0f;
+      prox(gx, gy, gz, wo[s][0], wo[s][1], wo[s][2], q[s][0], q[s][1], q[s][2]);
+      q0s[s][own_q] = q[s][0];
+      q1s[s][own_q] = q[s][1];
+      if (own && kk < kz1) {
+        const int p = own_ij + koff(kk);
+        w_out[p] = wo[s][0] + q[s][0];
+        w_out[ne + p] = wo[s][1] + q[s][1];
+        w_out[2 * ne + p] = wo[s][2] + q[s][2];
+      }
+    }
+    // lower-face dual steps (the component the own voxels need)
+    if (t < 64) {
+      float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+      const int kk = k + hpl;
+      if (h_ok && kk < kz1) {
+        const float *xs = hpl ? xc : xa, *xu = hpl ? xd : xc;
+        const float hv = xs[hb];
+        const float gx = (hgi < nx - 1) ? xs[hb + 1] - hv : 0.0f;
+        const float gy = (hgj < ny - 1) ? xs[hb + B] - hv : 0.0f;
+        const float gz = (kk < nz - 1) ? xu[hb] - hv : 0.0f;
+        prox(gx, gy, gz, wh[0], wh[1], wh[2], h0, h1, h2);
+      }
+      if ((t & 31) < 16)
+        q0s[hpl][hq] = h0;
+      else
+        q1s[hpl][hq] = h1;
+    }
+    __syncthreads();
+    // planes k+3, k+4 (loaded one step ago) replace k and k+1 in LDS
+    xb[bk0][own_b] = pxo0;
+    xb[bk1][own_b] = pxo1;
+    if (rb >= 0) xb[rpl ? bk1 : bk0][rb] = pxr;
+    pxo0 = nxo0;
+    pxo1 = nxo1;
+    pxr = nxr;
+    if (own) {
+      for (int s = 0; s < 2; ++s) {
+        const int kk = k + s;
+        if (kk >= kz1) break;
+        float dz = 0.0f;
+        if (i < nx - 1) dz -= q0s[s][own_q];
+        if (i > 0) dz += q0s[s][own_q - 1];
+        if (j < ny - 1) dz -= q1s[s][own_q];
+        if (j > 0) dz += q1s[s][own_q - Q];
+        if (kk < nz - 1) dz -= q[s][2];
+        if (kk > 0) dz += s ? q[0][2] : q2prev;
+        const int p = own_ij + koff(kk);
+        const float zn = zo[s] + dz;
+        const float zb = fmaf(dz, inv_p, zn);
+        z[p] = zn;
+        if (fuse)
+          x_out[p] = fmaxf(0.0f, fmaf(-to[s], zb, xv[s]));
+        else
+          zbar[p] = zb;
+      }
+    }
+    q2prev = q[1][2];
+    for (int s = 0; s < 2; ++s) {
+      zo[s] = nzo[s];
+      to[s] = nto[s];
+      for (int c = 0; c < 3; ++c) wo[s][c] = nwo[s][c];
+    }
+    for (int c = 0; c < 3; ++c) wh[c] = nwh[c];
+    // the buffer of plane k+2 becomes plane k of the next step
+    const int b0 = bk0, b1 = bk1;
+    bk0 = bk2;
+    bk1 = b0;
+    bk2 = b1;
     __syncthreads();
   }
 }
@@ -537,14 +573,10 @@ int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, 
                     hipStream_t st) {
   const long long ne = layout_size(L);
   if (L.sx == 2 && L.sy == 2 && L.sz == 2 && ncomp == 3) {
-    constexpr int CZ = 4;
+    constexpr int CZ = 16;
     const int nblocks = ((n[0] + 15) / 16) * ((n[1] + 15) / 16) * ((n[2] + CZ - 1) / CZ);
     hipLaunchKernelGGL((k_tv_march<CZ>), dim3(nblocks), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar, L.nbx,
                        L.nby, n[0], n[1], n[2], ne, Sp, beta, inv_p, fuse ? 1 : 0, nblocks);
-  } else if (L.sx == 2 && L.sy == 2 && L.sz == 2) {
-    const int ntiles = ((L.nbx + 1) / 2) * ((L.nby + 1) / 2) * L.nbz;
-    hipLaunchKernelGGL((k_tv_tiled<4, 4, 4, 2, 2>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar,
-                       L, n[0], n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0, ntiles);
   } else if (L.sx == 2 && L.sy == 2 && L.sz == 0 && n[2] == 1) {
     const int ntiles = ((L.nbx + 3) / 4) * ((L.nby + 3) / 4);
     hipLaunchKernelGGL((k_tv_tiled<4, 4, 1, 4, 4>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T,
