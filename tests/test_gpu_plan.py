@@ -374,3 +374,50 @@ def test_prior_updates_ragged_grids(P, shape):
     ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
     report(f"prior updates {shape}", x_err=ex, z_err=ez, w_l2=ew)
     assert ex <= ITER_TOL and ez <= ITER_TOL and ew <= ITER_TOL
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 11), (20, 33, 18)])
+def test_mixed_updates_ragged_grids(P, shape):
+    """Mixed data and prior updates from a random state on ragged 3D grids,
+    over two calls, against the oracle: data updates followed by prior
+    updates and by data updates, prior updates in a row, and calls that end
+    with either kind (the last update of a call materialises zbar instead
+    of fusing the next primal step)."""
+    nx, ny, nz = shape
+    sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
+    tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
+    img = lmsynth.ImageGeom((nx, ny, nz), (3.0, 2.5, 3.5))
+    p = lmsynth.simulate_3d(lmsynth.Problem("ragged", sc, img, tof, 4, 1, 0.03), n_prompts=20000, seed=78,
+                            workers=1)
+    n, beta = 4, 0.03
+    rng = np.random.default_rng(sum(shape) + 1)
+    zyx = (nz, ny, nx)
+    g = (5.0 + rng.uniform(0.0, 1.0, zyx)).astype(np.float32)
+    x_start = rng.uniform(0.5, 1.5, zyx).astype(np.float32)
+    z0 = (g + rng.uniform(-0.5, 0.5, zyx)).astype(np.float32)
+    zb0 = (g + rng.uniform(-0.5, 0.5, zyx)).astype(np.float32)
+    w0 = rng.normal(0.0, beta / 3, (3,) + zyx).astype(np.float32)
+    w0 *= np.minimum(1.0, beta / np.maximum(np.sqrt((w0.astype(np.float64) ** 2).sum(0)), 1e-30)).astype(np.float32)
+    c0 = rng.uniform(0.2, 0.8, len(p.events)).astype(np.float32)
+    Go = oracle.Geometry.from_problem(p)
+    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO)
+    st = oracle.LMState(x=x_start.astype(np.float64), z=z0.astype(np.float64), zbar=zb0.astype(np.float64),
+                        w=w0.astype(np.float64), y=1.0 - c0.astype(np.float64), u=0)
+    calls = [np.array([0, 4, 4, 1, 4, 2, 3, 4, 0, 4], np.int32), np.array([4, 1, 4, 2, 2, 4, 3, 4], np.int32)]
+    Gg, plan = _plan(P, p, n, g, beta)
+    cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+    plan.set_state({"z": cuda(z0), "zbar": cuda(zb0), "w": cuda(w0), "c": cuda(c0), "u": 0})
+    x = cuda(x_start)
+    for k, seq in enumerate(calls):
+        x_o, st, _ = oracle.lm_spdhg(Go, p.events, p.s.astype(np.float64), g.astype(np.float64), x_start, n, seq,
+                                     _gamma(p.x0), RHO, beta, setup=su, state=st)
+        plan.epoch(x, seq)
+        state = plan.get_state()
+        ex = img_err(x.cpu().numpy(), x_o)
+        ez = img_err(state["z"].cpu().numpy(), st.z)
+        ezb = img_err(state["zbar"].cpu().numpy(), st.zbar)
+        ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
+        wg = state["w"].cpu().numpy().astype(np.float64)
+        ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
+        report(f"mixed updates {shape} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
+        assert max(ex, ez, ezb, ec, ew) <= ITER_TOL
