@@ -376,7 +376,8 @@ def autograd_leg(torch, P, lmsynth, frames: int = 16, per_frame: int = 1_000_000
 # --------------------------------------------------------------------------- serving
 
 
-def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS):
+def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS, max_active: int = 8,
+                burst_test: bool = True):
     """64 Poisson-arrival requests served by Server, against the plain
     solver one request at a time on the same arrivals (its latencies follow
     from the measured service times of each request run alone)."""
@@ -425,7 +426,7 @@ def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS):
         fin = max(arrival[i], fin) + service[i]
         lat_seq[i] = fin - arrival[i]
 
-    srv = Server(hbm_budget=SERVE_BUDGET, device=dev, max_active=8)
+    srv = Server(hbm_budget=SERVE_BUDGET, device=dev, max_active=max_active)
     srv.warm(G_small, g_small)
     srv.warm(G3, g3)
     t0 = time.perf_counter()
@@ -440,7 +441,7 @@ def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS):
     st = latency_stats(res)
     # the same requests all at once: the server's throughput against the
     # solver's back-to-back total
-    burst = Server(hbm_budget=SERVE_BUDGET, device=dev, max_active=8)
+    burst = Server(hbm_budget=SERVE_BUDGET, device=dev, max_active=max_active)
     burst.warm(G_small, g_small)
     burst.warm(G3, g3)
     t0 = time.perf_counter()

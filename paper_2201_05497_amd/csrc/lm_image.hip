@@ -1,10 +1,14 @@
 // Image-space kernels of LM-SPDHG on gfx950: the primal step with the
 // non-negativity prox, the z / zbar updates, the TV dual update with its
-// adjoint stencil, and the tv_grad / tv_div entry points.
+// adjoint stencil, the layout conversions, and the tv_grad / tv_div entry
+// points.
 //
-// All of these stream whole images and are bound by memory bandwidth; each
-// thread handles one voxel, loads are coalesced along x (the fastest axis)
-// and every pass that can be fused with the next primal step is.
+// All of these stream whole images and are bound by memory bandwidth.  Plan
+// images are in 4x4x4-voxel bricks (4x4x1 for one slice); the element-wise
+// passes take one voxel per thread in layout order, the prior update stages
+// x through LDS (a tile for one slice, a column marching along z in 3D), and
+// every pass that can be fused with the next primal step is.  The
+// conversions and tv_grad / tv_div address the caller's row-major images.
 #include <hip/hip_runtime.h>
 
 #include "lm_host.hpp"
@@ -42,77 +46,6 @@ __global__ __launch_bounds__(kBlock) void k_dual_image(float *__restrict__ z, fl
     x[v] = fmaxf(0.0f, fmaf(-T[v], zb, x[v]));
   else
     zbar[v] = zb;
-}
-
-// w+ - w at voxel (i, j, k): the dual prior step evaluated from x and w
-// (three components; the z-component is zero when ncomp == 2).
-__device__ __forceinline__ void tv_step_at(const float *__restrict__ x, const float *__restrict__ w,
-                                           const lmk::Layout &L, int nx, int ny, int nz, long long ne, int ncomp,
-                                           float Sp, float beta, int i, int j, int k, float &q0, float &q1,
-                                           float &q2) {
-  const int p = lmk::vidx(L, i, j, k);
-  const float xv = x[p];
-  const float gx = (i < nx - 1) ? x[lmk::vidx(L, i + 1, j, k)] - xv : 0.0f;
-  const float gy = (j < ny - 1) ? x[lmk::vidx(L, i, j + 1, k)] - xv : 0.0f;
-  const float gz = (ncomp == 3 && k < nz - 1) ? x[lmk::vidx(L, i, j, k + 1)] - xv : 0.0f;
-  const float w0 = w[p], w1 = w[ne + p], w2 = (ncomp == 3) ? w[2 * ne + p] : 0.0f;
-  const float v0 = fmaf(Sp, gx, w0), v1 = fmaf(Sp, gy, w1), v2 = fmaf(Sp, gz, w2);
-  const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
-  const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
-  q0 = v0 * sc - w0;
-  q1 = v1 * sc - w1;
-  q2 = v2 * sc - w2;
-}
-
-// The whole prior update in one pass (the dual prior step, its
-// back-projection through K^T and the z / zbar step of Algorithm 2, fused
-// with the next primal step when `fuse` is set):
-//   q = proj_beta(w + S_prior K x) - w;  w_out = w + q;  dz = K^T q;
-//   z += dz;  zbar = z + dz / p;  fuse ? x_out = max(0, x - T zbar) : store zbar.
-// K^T q at a voxel needs q at the voxel and at its three lower neighbours;
-// each is recomputed here from x and w (the projection couples the three
-// components), so x and w are read-only and the results go to separate
-// buffers (x_out, w_out).
-__global__ __launch_bounds__(kBlock) void k_tv_fused(const float *__restrict__ x, const float *__restrict__ w,
-                                                     float *__restrict__ w_out, float *__restrict__ z,
-                                                     float *__restrict__ x_out, const float *__restrict__ T,
-                                                     float *__restrict__ zbar, lmk::Layout L, int nx, int ny,
-                                                     int nz, long long ne, int ncomp, float Sp, float beta,
-                                                     float inv_p, int fuse) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= ne) return;
-  int i, j, k;
-  lmk::vpos(L, p, i, j, k);
-  if (i >= nx || j >= ny || k >= nz) return;
-  float q0, q1, q2;
-  tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j, k, q0, q1, q2);
-  w_out[p] = w[p] + q0;
-  w_out[ne + p] = w[ne + p] + q1;
-  if (ncomp == 3) w_out[2 * ne + p] = w[2 * ne + p] + q2;
-  float d = 0.0f;
-  if (i < nx - 1) d -= q0;
-  if (j < ny - 1) d -= q1;
-  if (ncomp == 3 && k < nz - 1) d -= q2;
-  float a0, a1, a2;
-  if (i > 0) {
-    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i - 1, j, k, a0, a1, a2);
-    d += a0;
-  }
-  if (j > 0) {
-    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j - 1, k, a0, a1, a2);
-    d += a1;
-  }
-  if (ncomp == 3 && k > 0) {
-    tv_step_at(x, w, L, nx, ny, nz, ne, ncomp, Sp, beta, i, j, k - 1, a0, a1, a2);
-    d += a2;
-  }
-  const float zn = z[p] + d;
-  const float zb = fmaf(d, inv_p, zn);
-  z[p] = zn;
-  if (fuse)
-    x_out[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
-  else
-    zbar[p] = zb;
 }
 
 // The whole prior update, tiled through LDS (used for single-slice images;
@@ -582,8 +515,8 @@ int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, 
     hipLaunchKernelGGL((k_tv_tiled<4, 4, 1, 4, 4>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T,
                        zbar, L, n[0], n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0, ntiles);
   } else {
-    hipLaunchKernelGGL(k_tv_fused, dim3(grid_for(ne)), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar, L, n[0],
-                       n[1], n[2], ne, ncomp, Sp, beta, inv_p, fuse ? 1 : 0);
+    lmh::set_error("prior update: the image layout must be 4x4x4 bricks (or 4x4x1 for one slice)");
+    return LM_EINVAL;
   }
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;

@@ -201,7 +201,8 @@ def test_chunked_launches(P):
     P.lm_back(Gg, v[half:].contiguous(), evt[half:].contiguous(), parts)
     e = img_err(whole.cpu().numpy(), parts.cpu().numpy().astype(np.float64))
     report("chunked back vs halves", err=e)
-    assert e <= 1e-5
+    # both sides are FP32 atomic sums (~4e3 per voxel) in different orders
+    assert e <= BACK_TOL
 
 
 def test_sens_many_pairs(P):
