@@ -47,12 +47,6 @@ int make_geom(const lm_geom *G, lmk::GeomDev *out);
 // the per-lane sample cache of the projector kernels).
 int max_planes(const lmk::GeomDev &g, int mode);
 
-// Lanes per event and cached samples per lane for a plane bound.
-struct Launch {
-  int lpe;    // lanes per event: 16, 32 or 64
-  int jmax;   // samples per lane: 1, 2, 3, 4, 6 or 8
-};
-Launch pick_launch(int planes);
 
 // Voxel count with overflow check.
 inline long long nvox_of(const int n[3]) { return (long long)n[0] * n[1] * n[2]; }
