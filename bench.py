@@ -85,11 +85,11 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104950478, "write_bytes": 104101222, "sources": "ab177d4ad7e85d64",
+    "data_update": {"fetch_bytes": 104965236, "write_bytes": 104101080, "sources": "135d57dde2647586",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 129001239, "write_bytes": 76800614, "sources": "24f470e3501b5c0a",
+    "tv": {"fetch_bytes": 106583005, "write_bytes": 76867628, "sources": "3d65f9249db424b1",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "dual_image": {"fetch_bytes": 61408582, "write_bytes": 46080000, "sources": "39e1f5edc9acb210",
+    "dual_image": {"fetch_bytes": 61408621, "write_bytes": 46080000, "sources": "f91f190c9f75fbcc",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
 }
 
