@@ -155,9 +155,10 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
 
 /* Initialisation (Algorithm 2): y_e = 1 - mu_e / ((P^LM x0)_e + s_e),
  * w = 0, z = zbar = g + (P^LM)^T((y - 1)/mu) + K^T w.  (The printed
- * initialisation of z has "-" before the back projection; "+" is the sign under which z is the
- * back projection of the sinogram dual of Eq. yinit, as the text after the
- * algorithm states.)  Resets the update counter to 0. */
+ * initialisation of z has "-" before the back projection; "+" is the sign
+ * under which z is the back projection of the sinogram dual of Eq. yinit,
+ * as the text after the algorithm states.)  Resets the update counter to
+ * 0. */
 int lm_spdhg_init(lm_plan *p, const float *x0, void *stream);
 
 /* Runs n_updates updates of Algorithm 2.  seq_host (host) lists
@@ -223,7 +224,9 @@ int lm_plan_timing(lm_plan *p, int every);
 int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
 
 /* Synchronises the plan's last stream, then frees its device memory
- * stream-ordered on that stream (hipFreeAsync: no device-wide wait). */
+ * stream-ordered on that stream (hipFreeAsync: no device-wide wait).  That
+ * stream (the one of the plan's last call) must still exist.  A plan is not
+ * safe for concurrent use from several host threads. */
 int lm_plan_destroy(lm_plan *p);
 
 #ifdef __cplusplus

@@ -1,8 +1,9 @@
 // Device core of the listmode TOF Joseph projector (gfx950).
 //
-// One event is handled by a group of LPE lanes (LPE = 16, 32 or 64) of a
-// 64-wide wavefront; the lanes of a group walk the image planes of the
-// event's line of response, lane l taking planes m0 + l, m0 + l + LPE, ...
+// One event is handled by a group of LPE lanes of a 64-wide wavefront (8 in
+// the forward projector, the whole wavefront in the kernels that scatter);
+// the lanes of a group walk the image planes of the event's line of
+// response, lane l taking planes m0 + l, m0 + l + LPE, ...
 //
 // The per-event set-up (dominant axis, plane range, interpolation and TOF
 // coefficients) is done in double precision, once per event.  The
@@ -16,8 +17,9 @@
 // ([z][y][x], the caller's layout) or stored in bricks of 4x4x4 voxels (4x4x1
 // for a single slice), 256 bytes each, so that the few planes a ray spends
 // in a brick touch the same cache lines whatever the ray's direction.  The
-// FP32 atomics of the back projection are served per cache line, so the
-// number of lines one atomic instruction touches sets its cost.
+// FP32 atomics of the back projection are executed beyond the L2, one
+// request per memory sector that lanes of an instruction share, so the
+// sectors one atomic instruction touches set its cost.
 //
 // The functions below except the atomic scatters and group_sum are
 // __host__ __device__ so that the projector can also be exercised by a CPU
@@ -199,7 +201,9 @@ __host__ __device__ __forceinline__ Ray setup_ray(const GeomDev &g, int id1, int
   if (mhi_d < mlo_d) return r;
   const int m0 = (int)mlo_d;
   int np = (int)mhi_d - m0 + 1;
-  if (np > max_planes) np = max_planes;  // never reached for a valid plan bound
+  // max_planes (from max_planes() on the host) covers every plane of the
+  // TOF support; the clamp can only drop a margin plane of zero weight
+  if (np > max_planes) np = max_planes;
   r.nplanes = np;
   r.m0 = m0;
   r.a = a;
