@@ -36,6 +36,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -68,8 +69,9 @@ BYTES_PER_VOXEL = {"primal": 16, "dual_image": 28, "tv": 44}
 BYTES_PER_EVENT = 16 + 4 + 4 + 4 + 4
 BYTES_PER_EVENT_PROJ = 10 + 4
 
-# Sources that define each kernel class; their digest is compared with the
-# one recorded when the HBM traffic below was measured.
+# Sources that define each kernel class; their digest (code only, comments
+# and whitespace removed) is compared with the one recorded when the HBM
+# traffic below was measured.
 CSRC = os.path.join(HERE, "paper_2201_05497_amd", "csrc")
 KERNEL_SOURCES = {
     "data_update": ["lm_project.hip", "lm_device.hpp"],
@@ -85,11 +87,11 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104965236, "write_bytes": 104101080, "sources": "135d57dde2647586",
+    "data_update": {"fetch_bytes": 104965236, "write_bytes": 104101080, "sources": "13b85a0b20ad8c8c",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106583005, "write_bytes": 76867628, "sources": "3d65f9249db424b1",
+    "tv": {"fetch_bytes": 106583005, "write_bytes": 76867628, "sources": "e78091e9d6d9d6f0",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "dual_image": {"fetch_bytes": 61408621, "write_bytes": 46080000, "sources": "f91f190c9f75fbcc",
+    "dual_image": {"fetch_bytes": 61408621, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
 }
 
@@ -98,11 +100,19 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _code_only(src: str) -> str:
+    """C++ source without comments and whitespace (a comment edit does not
+    change the kernel)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return re.sub(r"\s+", "", src)
+
+
 def source_digest(cls: str) -> str:
     h = hashlib.sha1()
     for f in KERNEL_SOURCES[cls]:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(CSRC, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
