@@ -85,10 +85,11 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restr
   if (!src.get(g, e, id1, id2, k)) return;
   const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
   const float c = r.L * ve;
-  for (int j0 = 0; j0 < r.nplanes; j0 += 64) {
+  const int off = brick_offset(g.lay, r);
+  for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
     const int j = j0 + lane;
     Sample s = sample_at(g, r, j, g.tof_on);
-    const float cs = (j < r.nplanes) ? c * s.w : 0.0f;
+    const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
     scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
   }
 }
@@ -112,10 +113,11 @@ __global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, long long p0, long l
   while (i + 1 < nd && first(i + 1) <= p) ++i;
   const long long jdx = i + 1 + (p - first(i));
   const Ray r = setup_ray(g, (int)i, (int)jdx, 0, W_SUM, 1 << 20);
-  for (int j0 = 0; j0 < r.nplanes; j0 += 64) {
+  const int off = brick_offset(g.lay, r);
+  for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
     const int j = j0 + lane;
     Sample s = sample_at(g, r, j, g.tof_on);
-    const float cs = (j < r.nplanes) ? r.L * s.w : 0.0f;
+    const float cs = (j >= 0 && j < r.nplanes) ? r.L * s.w : 0.0f;
     scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
   }
 }
@@ -144,14 +146,15 @@ __global__ __launch_bounds__(kBlock) void k_data_update(GeomDev g, const float *
   const int4 rc = rec[e];
   const float Se = S[e];
   if (Se == 0.0f) return;  // LOR misses the image: the prox leaves y unchanged
-  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, JMAX * 64);
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, JMAX * 64 - kMaxBrickOffset);
+  const int off = brick_offset(g.lay, r);
   Sample cache[JMAX];
   float acc = 0.0f;
 #pragma unroll
   for (int jj = 0; jj < JMAX; ++jj) {
-    const int j = lane + jj * 64;
+    const int j = lane + jj * 64 - off;
     cache[jj] = sample_at(g, r, j, g.tof_on);
-    if (j < r.nplanes) {
+    if (j >= 0 && j < r.nplanes) {
       acc = fmaf(cache[jj].w, gather(g, x, r, cache[jj]), acc);
     } else {
       cache[jj].w = 0.0f;
@@ -169,7 +172,10 @@ __global__ __launch_bounds__(kBlock) void k_data_update(GeomDev g, const float *
   const float cf = r.L * (dy / me);
 #pragma unroll
   for (int jj = 0; jj < JMAX; ++jj) {
-    if (jj * 64 < r.nplanes) scatter_interleaved(g, dz, r, cache[jj], cf * cache[jj].w, lane, st.idx[wv], st.val[wv]);
+    if (jj * 64 - off < r.nplanes) {
+      const float cs = (cache[jj].w != 0.0f) ? cf * cache[jj].w : 0.0f;
+      scatter_interleaved(g, dz, r, cache[jj], cs, lane, st.idx[wv], st.val[wv]);
+    }
   }
 }
 
@@ -316,7 +322,9 @@ int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
 int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const float *S, const float *mu,
                        float *cdual, float *dz, long long n, hipStream_t st) {
   if (n == 0) return LM_OK;
-  const int planes = lmh::max_planes(g, W_BIN);
+  // the lanes of an event start up to kMaxBrickOffset planes before its
+  // first plane
+  const int planes = lmh::max_planes(g, W_BIN) + kMaxBrickOffset;
   const int jneed = (planes + 63) / 64;
 #define LM_DU(J_)                                                                                       \
   if (jneed <= J_) {                                                                                    \
