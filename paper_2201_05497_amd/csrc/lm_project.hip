@@ -54,7 +54,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, const float *__restri
   if (src.get(g, e, id1, id2, k)) {
     const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
     L = r.L;
-    for (int j = lane; j < r.nplanes; j += LPE) {
+    // lanes start at the brick boundary at or below the first plane, so
+    // that the LPE planes of one gather span as few bricks as possible
+    for (int j = lane - brick_offset(g.lay, r); j < r.nplanes; j += LPE) {
+      if (j < 0) continue;
       const Sample s = sample_at(g, r, j, g.tof_on);
       acc = fmaf(s.w, gather(g, x, r, s), acc);
     }
