@@ -96,6 +96,16 @@ PMC_TRAFFIC: dict = {
 }
 
 
+# FP32 atomic requests per event of the kernels that scatter, measured with
+# rocprofv3 --pmc TCC_ATOMIC_sum (all of them are executed beyond the L2:
+# TCC_EA0_ATOMIC_sum reads the same), with the digest of the kernel's
+# sources at the time.
+PMC_ATOMICS: dict = {}
+
+# Number of random positions of the atomic-rate calibration.
+ATOMIC_PROBE_N = 1 << 26
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -123,6 +133,57 @@ def traffic(cls: str):
     if t is None or t["sources"] != source_digest(cls):
         return None
     return int(t["fetch_bytes"] + t["write_bytes"])
+
+
+def atomic_requests_per_event(cls: str):
+    """Measured atomic requests per event of a kernel class, or None when
+    none were measured or the kernel's sources changed since."""
+    t = PMC_ATOMICS.get(cls)
+    if t is None or t["sources"] != source_digest(cls):
+        return None
+    return float(t["requests_per_event"])
+
+
+def calibrate_atomics(torch, dev, n_img: int = 3_840_000, reps: int = 10) -> float:
+    """Ceiling of the FP32 atomic request rate: index_add_ of ones at
+    ATOMIC_PROBE_N uniformly random positions of an image of n_img floats.
+    The 64 lanes of an instruction then almost never share a 64-byte
+    sector, so every lane-atomic is a request of its own; requests/s."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    idx = torch.randint(0, n_img, (ATOMIC_PROBE_N,), generator=gen, device=dev, dtype=torch.int64)
+    src = torch.ones(ATOMIC_PROBE_N, device=dev)
+    buf = torch.zeros(n_img, device=dev)
+    for _ in range(2):
+        buf.index_add_(0, idx, src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        buf.index_add_(0, idx, src)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = ATOMIC_PROBE_N * reps / (e0.elapsed_time(e1) * 1e-3)
+    del idx, src, buf
+    return rate
+
+
+def binding(cls: str, events_per_launch: float, us_per_launch: float, ceiling: float) -> dict:
+    """The resource that bounds a scattering kernel: its atomic requests
+    per second (measured requests per event x events per launch / live
+    launch duration) against the calibrated ceiling."""
+    out = {"kernel": cls, "resource": "FP32 atomic requests executed beyond the L2 (one per 64-byte sector "
+                                      "that lanes of an instruction share)",
+           "unit": "requests/s", "ceiling": float(f"{ceiling:.4g}"),
+           "ceiling_probe": f"torch index_add_ of {ATOMIC_PROBE_N} ones at random positions of 3.84e6 floats",
+           "achieved": None, "frac": None, "requests_per_launch": None, "sources": source_digest(cls)}
+    r = atomic_requests_per_event(cls)
+    if r is not None:
+        req = r * events_per_launch
+        achieved = req / (us_per_launch * 1e-6)
+        out.update(achieved=float(f"{achieved:.4g}"), frac=round(achieved / ceiling, 3),
+                   requests_per_launch=int(req))
+    return out
 
 
 def roofline(cls: str, bytes_per_launch: float, us_per_launch: float) -> dict:
@@ -270,6 +331,7 @@ def epoch_leg(args, torch, P, lmsynth):
     log(f"{args.steps} epochs in {t_total:.3f} s: {ms_per_step:.2f} ms/epoch, {value:.3e} events/s")
 
     roof = None
+    bind = None
     kernels = None
     if timing:
         nvox = G.nvox
@@ -294,6 +356,8 @@ def epoch_leg(args, torch, P, lmsynth):
         else:
             bpl = BYTES_PER_VOXEL[dom] * nvox
         roof = roofline(dom, bpl, kernels[dom]["us_avg"])
+        if dom == "data_update":
+            bind = binding(dom, n_proj / n_data, kernels[dom]["us_avg"], calibrate_atomics(torch, dev))
 
     out = {
         "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
@@ -313,6 +377,7 @@ def epoch_leg(args, torch, P, lmsynth):
                                "TV beta 0.03, one LM-SPDHG epoch per step",
                    "events": len(p.events), "subsets": N_SUB, "image": list(G.shape)},
         "roofline": roof,
+        "binding": bind,
         "kernels": kernels,
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create": round(t_plan, 3)},
     }
@@ -547,6 +612,9 @@ def large_leg(args, torch, P, lmsynth):
         kernels = {k: {"us_avg": round(1e3 * ms / c, 2), "timed_launches": c} for k, (ms, c) in timing.items() if c}
 
     roof = roofline("back", BYTES_PER_EVENT_PROJ * N, t_back * 1e3)
+    # lm_back runs as consecutive launches; the requests per event do not
+    # depend on the launch size, so the whole call stands for one launch
+    bind = binding("back", N, t_back * 1e3, calibrate_atomics(torch, dev))
     return {
         "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
         "value": round(value, 1),
@@ -569,6 +637,7 @@ def large_leg(args, torch, P, lmsynth):
                  "back_events_per_s": round(N / (t_back * 1e-3), 1),
                  "algorithmic_GBs": round(2 * BYTES_PER_EVENT_PROJ * N / (t_pass * 1e-3) / 1e9, 1)},
         "roofline": roof,
+        "binding": bind,
         "kernels": kernels,
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create_init": round(t_plan, 3)},
     }, p

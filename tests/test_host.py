@@ -79,6 +79,22 @@ def test_bench_traffic_guarded_by_source_digest(monkeypatch):
     assert "traffic_GBs" not in bench.roofline("data_update", 1e6, 100.0)
 
 
+def test_bench_binding_guarded_by_source_digest(monkeypatch):
+    """The atomic request rate is reported only while the kernel's sources
+    are the ones its requests per event were measured on."""
+    sys.path.insert(0, ROOT)
+    import importlib
+    bench = importlib.import_module("bench")
+    dig = bench.source_digest("data_update")
+    monkeypatch.setitem(bench.PMC_ATOMICS, "data_update", {"requests_per_event": 50.0, "sources": dig})
+    b = bench.binding("data_update", 40_000, 100.0, 2.0e10)
+    assert b["requests_per_launch"] == 2_000_000
+    assert b["achieved"] == pytest.approx(2.0e10) and b["frac"] == pytest.approx(1.0)
+    monkeypatch.setitem(bench.PMC_ATOMICS, "data_update", {"requests_per_event": 50.0, "sources": "0" * 16})
+    b = bench.binding("data_update", 40_000, 100.0, 2.0e10)
+    assert b["achieved"] is None and b["frac"] is None and b["ceiling"] == 2.0e10
+
+
 def test_product_package_never_imports_the_oracle():
     """The product path runs only the library's kernels: no module of the
     package imports the oracle (which is test infrastructure)."""
