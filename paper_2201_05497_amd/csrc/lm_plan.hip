@@ -260,14 +260,15 @@ int dalloc(lm_plan *p, T **ptr, size_t count) {
 // Device memory is allocated and freed stream-ordered (hipMallocAsync /
 // hipFreeAsync on the plan's last stream): neither implies a device-wide
 // synchronisation, so plans of other streams keep running meanwhile.
+// Release errors are not reported: the plan is gone either way.
 void free_plan(lm_plan *p) {
-  for (void *q : p->allocs) hipFreeAsync(q, p->last);
+  for (void *q : p->allocs) (void)hipFreeAsync(q, p->last);
   p->allocs.clear();
   for (auto &e : p->ev_pending) {
-    hipEventDestroy(e.second.first);
-    hipEventDestroy(e.second.second);
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
   }
-  for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -337,7 +338,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
     unsigned long long hb = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFreeAsync(bad, st);
+    (void)hipFreeAsync(bad, st);
     LM_TRY_HIP(e);
     LM_REQUIRE(hb == 0, LM_ERANGE, "%llu events have a crystal, ring or TOF index out of range", hb);
   }
@@ -387,11 +388,11 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, cap * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&slot, std::max<long long>(N, 1) * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&ones, E * sizeof(float), st);
-  auto free_tmp = [&]() {
-    if (keys) hipFreeAsync(keys, st);
-    if (cnt) hipFreeAsync(cnt, st);
-    if (slot) hipFreeAsync(slot, st);
-    if (ones) hipFreeAsync(ones, st);
+  auto free_tmp = [&]() {  // release errors are not reported
+    if (keys) (void)hipFreeAsync(keys, st);
+    if (cnt) (void)hipFreeAsync(cnt, st);
+    if (slot) (void)hipFreeAsync(slot, st);
+    if (ones) (void)hipFreeAsync(ones, st);
   };
   if (e != hipSuccess) {
     free_tmp();

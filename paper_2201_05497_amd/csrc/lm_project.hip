@@ -368,7 +368,7 @@ struct BrickImage {
     return LM_OK;
   }
   ~BrickImage() {
-    if (p) hipFreeAsync(p, st);
+    if (p) (void)hipFreeAsync(p, st);  // a release error has no caller to go to
   }
 };
 
@@ -438,7 +438,7 @@ int lm_validate_events(const lm_geom *G, const int16_t *ev, int64_t n, int64_t *
   unsigned long long h = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFreeAsync(d, st);
+  (void)hipFreeAsync(d, st);
   LM_TRY_HIP(e);
   *n_bad = (int64_t)h;
   return LM_OK;
