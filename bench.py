@@ -87,11 +87,11 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104965236, "write_bytes": 104101080, "sources": "13b85a0b20ad8c8c",
+    "data_update": {"fetch_bytes": 104911771, "write_bytes": 98294765, "sources": "8f1d8fa221d09f41",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106583005, "write_bytes": 76867628, "sources": "e78091e9d6d9d6f0",
+    "tv": {"fetch_bytes": 106583381, "write_bytes": 76866647, "sources": "1fdedec9cc26a97f",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "dual_image": {"fetch_bytes": 61408621, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
+    "dual_image": {"fetch_bytes": 61408660, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
 }
 
@@ -100,7 +100,12 @@ PMC_TRAFFIC: dict = {
 # rocprofv3 --pmc TCC_ATOMIC_sum (all of them are executed beyond the L2:
 # TCC_EA0_ATOMIC_sum reads the same), with the digest of the kernel's
 # sources at the time.
-PMC_ATOMICS: dict = {}
+PMC_ATOMICS: dict = {
+    "data_update": {"requests_per_event": 47.29, "sources": "8f1d8fa221d09f41",
+        "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
+    "back": {"requests_per_event": 66.97, "sources": "8f1d8fa221d09f41",
+        "profile": "profiles/pass_3d_300x300x96_counters.txt"},
+}
 
 # Number of random positions of the atomic-rate calibration.
 ATOMIC_PROBE_N = 1 << 26
