@@ -339,7 +339,7 @@ int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const 
     }                                                                                                   \
     return LM_OK;                                                                                       \
   }
-  LM_DU(1) LM_DU(2) LM_DU(3) LM_DU(4) LM_DU(6) LM_DU(8)
+  LM_DU(1) LM_DU(2) LM_DU(3) LM_DU(4) LM_DU(6) LM_DU(9)
 #undef LM_DU
   lmh::set_error("no update kernel for %d planes per event", planes);
   return LM_EINVAL;

@@ -11,7 +11,7 @@ import torch
 
 import lmsynth
 import oracle
-from tests.helpers import img_err, problem_2d, problem_3d, proj_err, report
+from tests.helpers import img_err, problem_2d, problem_3d, proj_err, report, smooth_image
 
 pytestmark = pytest.mark.gpu
 
@@ -287,6 +287,35 @@ def test_errors_and_degenerate_inputs(P):
     none.init(x)
     none.epoch(x, [3, 0, 3])
     assert torch.isfinite(x).all()
+
+
+def test_widest_update_configuration(P):
+    """A non-TOF plan on the largest supported image (512 x 512): events
+    visit up to 512 planes, plus up to three lanes before the first plane
+    (the lanes of the fused update start at a brick boundary), which takes
+    the widest configuration of the fused update.  One epoch against the
+    oracle."""
+    p = lmsynth.tiny_2d(n_det=64, nxy=512, h=0.5, radius=400.0, tof_on=False)
+    Go = oracle.Geometry.from_problem(p, tof_on=False)
+    Gg = P.Geometry.from_problem(p, tof_on=False)
+    ev = lmsynth.random_events(p, 400, seed=21, min_sep=20)
+    s = np.random.default_rng(22).uniform(0.5, 1.5, len(ev)).astype(np.float32)
+    x0 = smooth_image(Go.shape, 23)
+    g = oracle.sens(Go).astype(np.float32)
+    n_sub, beta = 4, 0.03
+    gamma = _gamma(x0)
+    plan = P.Plan(Gg, Gg.events(ev), torch.as_tensor(s, device="cuda"), n_sub, gamma, RHO, beta,
+                  g=torch.as_tensor(g, device="cuda"))
+    x = torch.as_tensor(x0, device="cuda").clone()
+    plan.init(x)
+    seq = lmsynth.subset_sequence(25, 0, 2 * n_sub, n_sub)  # 5 data and 3 prior updates
+    plan.epoch(x, seq)
+    x_o, _, _ = oracle.lm_spdhg(Go, ev, s.astype(np.float64), g.astype(np.float64), x0, n_sub, seq, gamma, RHO,
+                                beta)
+    e = img_err(x.cpu().numpy(), x_o)
+    report("512x512 non-TOF epoch", x_err=e, data_updates=int((np.asarray(seq) < n_sub).sum()))
+    assert e <= ITER_TOL
+    plan.destroy()
 
 
 def test_empty_subsets_match_oracle(P):
