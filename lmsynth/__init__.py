@@ -533,6 +533,26 @@ def simulate_3d(p: Problem, n_prompts: int = 10_000_000, contam_frac: float = 0.
     return _finish(rng, trues, contam, s[:n_t], s[n_t:], p, seed)
 
 
+def sort_by_dominant_axis(p: Problem, chunk: int = 10_000_000) -> Problem:
+    """Reorders the events (and s) of `p` in place, stably, by the dominant
+    axis of each event's line of response: the coordinate along which its
+    two crystals differ most (the lower axis on ties).  This is the input
+    order of the long static frame, whose events come grouped by dominant
+    axis; inside a group the chronological order is kept.  Returns `p`."""
+    det = p.det
+    n = len(p.events)
+    axis = np.empty(n, dtype=np.uint8)
+    for a in range(0, n, chunk):
+        ev = p.events[a:a + chunk].astype(np.int64)
+        d = np.abs(det[ev[:, 2] + p.scanner.n_cry * ev[:, 3]] - det[ev[:, 0] + p.scanner.n_cry * ev[:, 1]])
+        axis[a:a + chunk] = np.argmax(d, axis=1)  # first maximum: the lower axis
+    order = np.argsort(axis, kind="stable")
+    del axis
+    p.events = np.ascontiguousarray(p.events[order])
+    p.s = np.ascontiguousarray(p.s[order])
+    return p
+
+
 def uniform_x0(p: Problem, n_trues: int, radius: float, rng, n_mc: int = 200_000) -> np.ndarray:
     """Uniform starting image inside a cylinder of the given radius, scaled so
     that the summed line integrals over all LORs match the number of trues:

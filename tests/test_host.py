@@ -133,3 +133,25 @@ def test_plan_bytes_grow_with_events_and_image():
     # per event: the record (16 B) and five 4-byte lists persist, plus the
     # hash table of plan creation
     assert plan_bytes(2000, (16, 16, 8)) - a >= 1000 * 40
+
+
+def test_sort_by_dominant_axis():
+    """The large workload's input order: grouped by dominant axis (x, then
+    y, then z), chronological inside each group, the same events and s."""
+    p = lmsynth.simulate_3d(lmsynth.config_3d(), n_prompts=300_000, seed=7, workers=1)
+    ev0, s0 = p.events.copy(), p.s.copy()
+    lmsynth.sort_by_dominant_axis(p, chunk=70_000)
+    det = p.det  # float32, as the ordering computes it
+    nc = p.scanner.n_cry
+    d = np.abs(det[p.events[:, 2] + nc * p.events[:, 3].astype(np.int64)]
+               - det[p.events[:, 0] + nc * p.events[:, 1].astype(np.int64)])
+    axis = np.argmax(d, axis=1)
+    assert np.all(np.diff(axis) >= 0) and axis.min() == 0 and axis.max() >= 1
+    # a permutation of the same (event, s) pairs, chronological inside a group
+    key0 = np.concatenate([ev0.astype(np.int64), s0.view(np.int32)[:, None]], axis=1)
+    key1 = np.concatenate([p.events.astype(np.int64), p.s.view(np.int32)[:, None]], axis=1)
+    assert np.array_equal(np.unique(key0, axis=0), np.unique(key1, axis=0))
+    for a in np.unique(axis):
+        grp = key1[axis == a]
+        d0 = np.abs(det[ev0[:, 2] + nc * ev0[:, 3].astype(np.int64)] - det[ev0[:, 0] + nc * ev0[:, 1].astype(np.int64)])
+        assert np.array_equal(grp, key0[np.argmax(d0, axis=1) == a])
