@@ -353,16 +353,6 @@ __host__ __device__ __forceinline__ float gather(const GeomDev &g, const float *
   return fmaf(s.f2, hi - lo, lo);
 }
 
-// Bilinear scatter-add of c into the four corners (one atomic per corner).
-__device__ __forceinline__ void scatter(const GeomDev &g, float *img, const Ray &r, const Sample &s, float c) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float wc;
-    const int ix = corner(g, r, s, q, wc);
-    if (ix >= 0 && wc != 0.0f) atomicAdd(img + ix, c * wc);
-  }
-}
-
 // Kernels that scatter start their lanes at the brick boundary at or below
 // a ray's first plane: lane l of chunk c takes plane offset
 // j = 64 c + l - brick_offset, so that the 16-plane rounds of the
