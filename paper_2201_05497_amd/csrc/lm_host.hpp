@@ -83,6 +83,9 @@ int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n,
 int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img,
                 hipStream_t st);
 int launch_sens(const GeomDev &g, float *img, hipStream_t st);
+// Sensitivity by transaxial line (lm_lines.hip) for cylindrical 3D
+// scanners; `done` is false when the geometry does not qualify.
+int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done);
 // Plan-internal event records: int4 {id1, id2, k, s bits}.
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
                    hipStream_t st);

@@ -1,0 +1,371 @@
+// Back projection organised by transaxial line, for cylindrical scanners
+// (crystal c of ring r at (x_c, y_c, z_r)): the sensitivity image P^T 1.
+//
+// Every line of response between crystals c1 != c2 of any two rings has the
+// same transaxial projection, so when its dominant axis is transaxial it
+// meets the image planes at the same transaxial positions: only its z
+// coordinate, its length and its TOF window depend on the rings.  A
+// wavefront owns one transaxial line and 64 consecutive planes (lane l:
+// plane M0 + l) and accumulates the contributions of all LORs on that line
+// into LDS columns acc[corner][z][lane] (the two transaxial corners of the
+// lane's plane, every z), each lane only touching its own column.  The
+// columns are added to the image once per wavefront, so the image sees one
+// atomic per touched voxel and line instead of one per LOR and voxel.  LORs
+// whose dominant axis is z (short transaxial chords, large ring
+// differences) keep the per-LOR projector.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lm_device.hpp"
+#include "lm_host.hpp"
+
+using namespace lmk;
+
+namespace {
+
+constexpr int kLanes = 64;
+
+// Transaxial part of a line from crystal c1 to crystal c2 of ring 0 and the
+// lane's plane on it.
+struct LineLane {
+  int a;            // dominant transaxial axis (0: x, 1: y)
+  int nb;           // image size along the other transaxial axis
+  float fdx, fdy;   // float32 transaxial differences (dominant-axis decisions)
+  double dxy2;      // squared transaxial length
+  double ha_over_da;  // h_a / |d_a|
+  bool active;      // the lane's plane lies on the LOR (lam in [0, 1])
+  int m;            // the lane's plane
+  double lam;       // LOR parameter at the plane
+  int i1;           // lower transaxial corner (may be -1 or nb - 1)
+  float f1;         // its fractional weight
+};
+
+// Pair index p of the row-major upper triangle of an n x n matrix (c1 < c2).
+__device__ __forceinline__ void pair_of(long long p, int n, int &c1, int &c2) {
+  const double b = 2.0 * n - 1.0;
+  long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+  auto first = [&](long long r) { return r * n - r * (r + 1) / 2; };
+  if (i < 0) i = 0;
+  while (i > 0 && first(i) > p) --i;
+  while (i + 1 < n && first(i + 1) <= p) ++i;
+  c1 = (int)i;
+  c2 = (int)(i + 1 + (p - first(i)));
+}
+
+__device__ __forceinline__ LineLane line_lane(const GeomDev &g, int c1, int c2, int m0, int lane) {
+  LineLane q;
+  const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
+  q.fdx = d2[0] - d1[0];
+  q.fdy = d2[1] - d1[1];
+  q.a = (fabsf(q.fdy) > fabsf(q.fdx)) ? 1 : 0;
+  const int b = 1 - q.a;
+  const double p1a = q.a ? d1[1] : d1[0], da = q.a ? (double)d2[1] - d1[1] : (double)d2[0] - d1[0];
+  const double p1b = b ? d1[1] : d1[0], db = b ? (double)d2[1] - d1[1] : (double)d2[0] - d1[0];
+  const double dx = (double)d2[0] - d1[0], dy = (double)d2[1] - d1[1];
+  q.dxy2 = dx * dx + dy * dy;
+  const double ha = g.h[q.a], c0a = g.c0[q.a], hb = g.h[b], c0b = g.c0[b];
+  const int na = g.n[q.a];
+  q.nb = g.n[b];
+  q.ha_over_da = ha / fabs(da);
+  q.m = m0 + lane;
+  q.active = false;
+  q.lam = 0.0;
+  q.i1 = -2;
+  q.f1 = 0.0f;
+  if (da == 0.0 || q.m >= na) return q;
+  const double lam0 = (c0a - p1a) / da, dlam = ha / da;
+  const double m_at0 = -lam0 / dlam, m_at1 = (1.0 - lam0) / dlam;
+  const double mlo = ceil(fmin(m_at0, m_at1)), mhi = floor(fmax(m_at0, m_at1));
+  if ((double)q.m < mlo || (double)q.m > mhi) return q;
+  q.lam = lam0 + q.m * dlam;
+  const double u1 = (p1b + q.lam * db - c0b) / hb;
+  const double fl = floor(u1);
+  if (fl < -1.0 || fl > (double)q.nb - 1.0) return q;  // both corners outside
+  q.i1 = (int)fl;
+  q.f1 = (float)(u1 - fl);
+  q.active = true;
+  return q;
+}
+
+// Per-LOR coefficients of a line's LOR (rings at z1, z2; TOF centre tc and
+// half-width `edge` of the weight's bin range; value v): with the lane's
+// LOR parameter lam, the TOF argument is vh = A - lam B (units of
+// sigma sqrt 2), vl = vh - D, and the z coordinate in voxels is az + lam bz.
+struct Lor {
+  double A, B, az, bz;
+  float D, c;  // c = v L
+};
+
+// The z coefficients first (cheap, they decide whether the LOR touches a
+// wavefront's z part), then the rest.
+__device__ __forceinline__ void lor_z(const GeomDev &g, double ihz, double z1, double z2, Lor &o) {
+  o.az = (z1 - g.c0[2]) * ihz;
+  o.bz = (z2 - z1) * ihz;
+}
+
+__device__ __forceinline__ void lor_rest(const GeomDev &g, const LineLane &q, double z1, double z2, double tc,
+                                         double edge, float v, Lor &o) {
+  const double dz = z2 - z1;
+  const double dn = sqrt(q.dxy2 + dz * dz);
+  // t(lam) = (lam - 1/2) dn, vh = (tc + edge - t) / (sigma sqrt 2)
+  o.A = (tc + edge + 0.5 * dn) * g.inv_sr2;
+  o.B = dn * g.inv_sr2;
+  o.D = (float)(2.0 * edge * g.inv_sr2);
+  o.c = v * (float)(q.ha_over_da * dn);
+}
+
+// A wavefront's share of the columns: z in [zlo, zlo + zc), acc[cb][z - zlo][lane].
+struct ZPart {
+  int zlo, zc;
+};
+
+// Adds one LOR's samples at the lane's plane to the lane's column.  wfull is
+// the weight of a sample whose TOF argument covers the whole truncated
+// Gaussian (vh >= vclip and vl <= -vclip), the same value tof_weight gives
+// for it, so that such samples skip the two erfc evaluations.
+__device__ __forceinline__ void add_lor(const GeomDev &g, const LineLane &q, const Lor &o, const ZPart &zp,
+                                        float wfull, float *acc, int nz, int lane) {
+  if (!q.active) return;
+  float c = o.c;
+  if (g.tof_on) {
+    const float vh = (float)fma(-q.lam, o.B, o.A), vl = vh - o.D;
+    c *= (vh >= g.vclip && vl <= -g.vclip) ? wfull : tof_weight(vh, vl, g.vclip, g.inv_norm);
+  }
+  if (c == 0.0f) return;
+  const double u2 = fma(q.lam, o.bz, o.az);
+  const double fl = floor(u2);
+  if (fl < -1.0 || fl > (double)nz - 1.0) return;
+  const int k0 = (int)fl;
+  const float f2 = (float)(u2 - fl);
+  // the four corners are distinct entries of the lane's own column (no
+  // other lane or wavefront touches it): all reads first, then all writes,
+  // so that their LDS latencies overlap
+  bool ok[4];
+  float *ad[4];
+  float w[4], old[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int cb = t >> 1, cz = t & 1;
+    const int kz = k0 + cz - zp.zlo;
+    ok[t] = (unsigned)(q.i1 + cb) < (unsigned)q.nb && (unsigned)kz < (unsigned)zp.zc && k0 + cz < nz;
+    ad[t] = acc + ((cb * zp.zc + (ok[t] ? kz : 0)) * kLanes + lane);
+    w[t] = c * (cb ? q.f1 : 1.0f - q.f1) * (cz ? f2 : 1.0f - f2);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) old[t] = ok[t] ? *ad[t] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (ok[t]) *ad[t] = old[t] + w[t];
+}
+
+// Adds the lane's columns to the image: one atomic per non-zero voxel.
+__device__ __forceinline__ void flush(const GeomDev &g, const LineLane &q, const ZPart &zp, const float *acc,
+                                      float *img, int lane) {
+  const Layout &L = g.lay;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int ib = q.i1 + cb;
+    const bool ok = q.active && (unsigned)ib < (unsigned)q.nb;
+    const int i = q.a == 0 ? q.m : ib, j = q.a == 0 ? ib : q.m;
+    const int base = ok ? vidx(L, i, j, 0) : 0;
+    for (int kz = 0; kz < zp.zc; ++kz) {
+      const float v = acc[(cb * zp.zc + kz) * kLanes + lane];
+      if (ok && v != 0.0f) atomicAdd(img + (base + vidx(L, 0, 0, zp.zlo + kz)), v);
+    }
+  }
+}
+
+// z extent of a part: 2 x kZPart x 64 floats of LDS per wavefront.
+constexpr int kZPart = 32;
+
+// Sensitivity over the LORs of every line c1 < c2 whose dominant axis is
+// transaxial: all ring pairs (r1, r2), the TOF weight summed over all bins.
+// Block b (one wavefront): line b / (nchunk nzp), planes 64 chunk .. + 63
+// with chunk = (b / nzp) % nchunk, and z part b % nzp.  A LOR whose z range
+// over the chunk's planes misses the part is skipped on uniform values.
+__global__ __launch_bounds__(kLanes) void k_sens_lines(GeomDev g, long long p0, long long nlines, int nchunk,
+                                                       int nzp, float *img) {
+  __shared__ float acc[2 * kZPart * kLanes];
+  const long long blk = (long long)blockIdx.x;
+  const long long per_line = (long long)nchunk * nzp;
+  if (blk / per_line >= nlines) return;
+  const long long p = p0 + blk / per_line;
+  const int chunk = (int)((blk / nzp) % nchunk), part = (int)(blk % nzp);
+  const int lane = threadIdx.x;
+  const int nz = g.n[2];
+  ZPart zp;
+  zp.zlo = part * kZPart;
+  zp.zc = min(kZPart, nz - zp.zlo);
+  int c1, c2;
+  pair_of(p, g.n_cry, c1, c2);
+  const LineLane q = line_lane(g, c1, c2, chunk * kLanes, lane);
+  const unsigned long long act = __ballot(q.active);
+  if (act == 0) return;  // the chunk misses the line
+  // LOR parameter at the first and last active plane of the chunk
+  const int la = __ffsll((long long)act) - 1, lb = 63 - __clzll((long long)act);
+  const double lam_a = __shfl(q.lam, la), lam_b = __shfl(q.lam, lb);
+  for (int i = lane; i < 2 * zp.zc * kLanes; i += kLanes) acc[i] = 0.0f;
+  const double edge = (g.kmax + 0.5) * g.tof_bin;  // all bins: centre 0
+  const float wfull = tof_weight(g.vclip, -g.vclip, g.vclip, g.inv_norm);
+  const int nr = g.n_ring;
+  const double ihz = 1.0 / g.h[2];
+  auto zring = [&](int r) { return g.det[3 * (g.n_cry * r) + 2]; };
+  for (int r1 = 0; r1 < nr; ++r1) {
+    const float z1f = zring(r1);
+    // The LOR (r1, r2) can touch the part when its corners over the chunk,
+    // floor(u) - 1 .. floor(u) + 2 for u between ua and ub (one voxel of
+    // margin on each side for rounding between the end planes), reach
+    // [zlo, zlo + zc).  With z increasing with the ring (checked on the
+    // host) both bounds grow with r2, so those r2 form one interval, found
+    // by bisection on the same expressions.
+    auto u_ends = [&](int r2, double &umin, double &umax) {
+      Lor o;
+      lor_z(g, ihz, z1f, zring(r2), o);
+      const double ua = fma(lam_a, o.bz, o.az), ub = fma(lam_b, o.bz, o.az);
+      umin = fmin(ua, ub);
+      umax = fmax(ua, ub);
+    };
+    auto reaches_lo = [&](int r2) {  // floor(umax) + 2 >= zlo
+      double umin, umax;
+      u_ends(r2, umin, umax);
+      return floor(umax) + 2.0 >= (double)zp.zlo;
+    };
+    auto below_hi = [&](int r2) {  // floor(umin) - 1 < zlo + zc
+      double umin, umax;
+      u_ends(r2, umin, umax);
+      return floor(umin) - 1.0 < (double)(zp.zlo + zp.zc);
+    };
+    int lo = 0, hi = nr;  // first r2 with reaches_lo
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (reaches_lo(mid)) hi = mid; else lo = mid + 1;
+    }
+    const int r2a = lo;
+    lo = r2a;
+    hi = nr;  // first r2 >= r2a without below_hi
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (below_hi(mid)) lo = mid + 1; else hi = mid;
+    }
+    const int r2b = lo;
+    for (int r2 = r2a; r2 < r2b; ++r2) {
+      const float z2f = zring(r2);
+      if (dominant_axis(q.fdx, q.fdy, z2f - z1f) == 2) continue;  // per-LOR path
+      Lor o;
+      lor_z(g, ihz, z1f, z2f, o);
+      lor_rest(g, q, z1f, z2f, 0.0, edge, 1.0f, o);
+      add_lor(g, q, o, zp, wfull, acc, nz, lane);
+    }
+  }
+  flush(g, q, zp, acc, img, lane);
+}
+
+// Stage for the per-LOR scatter (one wavefront per block).
+struct Stage1 {
+  int idx[256];
+  float val[256];
+};
+
+// Sensitivity over the LORs the line kernel leaves out: those whose
+// dominant axis is z.  Block p: crystals c1 <= c2 (the pair index of the
+// upper triangle with its diagonal); ring pairs (r1, r2) for c1 < c2 and
+// r1 < r2 for c1 = c2.
+__global__ __launch_bounds__(kLanes) void k_sens_zdom(GeomDev g, long long p0, long long np, float *img) {
+  __shared__ Stage1 st;
+  const long long q = (long long)blockIdx.x;
+  if (q >= np) return;
+  const int lane = threadIdx.x;
+  int c1, c2;
+  // pairs with the diagonal: index p of an (n+1) x (n+1) upper triangle
+  pair_of(p0 + q, g.n_cry + 1, c1, c2);
+  c2 -= 1;
+  const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
+  const float fdx = d2[0] - d1[0], fdy = d2[1] - d1[1];
+  const int nr = g.n_ring;
+  for (long long rr0 = 0; rr0 < (long long)nr * nr; rr0 += kLanes) {
+    const long long rr = rr0 + lane;
+    bool zdom = false;
+    int r1 = 0, r2 = 0;
+    if (rr < (long long)nr * nr) {
+      r1 = (int)(rr / nr);
+      r2 = (int)(rr % nr);
+      const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
+      zdom = (c1 != c2 || r1 < r2) && dominant_axis(fdx, fdy, z2f - z1f) == 2;
+    }
+    unsigned long long mask = __ballot(zdom);
+    while (mask) {
+      const int src = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const int s1 = __shfl(r1, src), s2 = __shfl(r2, src);
+      const Ray r = setup_ray(g, c1 + g.n_cry * s1, c2 + g.n_cry * s2, 0, W_SUM, 1 << 20);
+      const int off = brick_offset(g.lay, r);
+      for (int j0 = -off; j0 < r.nplanes; j0 += kLanes) {
+        const int j = j0 + lane;
+        Sample s = sample_at(g, r, j, g.tof_on);
+        const float cs = (j >= 0 && j < r.nplanes) ? r.L * s.w : 0.0f;
+        scatter_interleaved(g, img, r, s, cs, lane, st.idx, st.val);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+namespace lmk {
+
+// The scanner is cylindrical when crystal c of ring r sits at (x_c, y_c, z_r):
+// the same transaxial position in every ring and one z per ring, with z_r
+// increasing in r.
+static int cylindrical(const GeomDev &g, hipStream_t st, bool &yes) {
+  std::vector<float> d((size_t)g.n_det * 3);
+  LM_TRY_HIP(hipMemcpyAsync(d.data(), g.det, d.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+  LM_TRY_HIP(hipStreamSynchronize(st));
+  yes = true;
+  for (int r = 0; r < g.n_ring && yes; ++r)
+    for (int c = 0; c < g.n_cry; ++c) {
+      const float *p = &d[3 * ((size_t)g.n_cry * r + c)];
+      if (p[0] != d[3 * c] || p[1] != d[3 * c + 1] || p[2] != d[3 * (size_t)g.n_cry * r + 2]) {
+        yes = false;
+        break;
+      }
+    }
+  for (int r = 1; r < g.n_ring && yes; ++r)
+    if (!(d[3 * (size_t)g.n_cry * r + 2] > d[3 * (size_t)g.n_cry * (r - 1) + 2])) yes = false;
+  return LM_OK;
+}
+
+// Sensitivity by transaxial line; returns LM_OK with `done` false when the
+// scanner or image does not qualify (the caller then uses the per-LOR
+// kernel).
+int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done) {
+  done = false;
+  if (g.n_ring < 2 || g.n_cry < 2) return LM_OK;
+  bool cyl = false;
+  if (int rc = cylindrical(g, st, cyl)) return rc;
+  if (!cyl) return LM_OK;
+  const int na_max = std::max(g.n[0], g.n[1]);
+  const int nchunk = (na_max + kLanes - 1) / kLanes;
+  const int nzp = (g.n[2] + kZPart - 1) / kZPart;
+  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
+  // at most 2^24 blocks of 64 work-items per launch
+  const long long per = std::max<long long>(1, (1LL << 24) / ((long long)nchunk * nzp));
+  for (long long p0 = 0; p0 < nlines; p0 += per) {
+    const long long m = std::min(per, nlines - p0);
+    hipLaunchKernelGGL(k_sens_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, p0, m, nchunk,
+                       nzp, img);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  const long long npz = (long long)g.n_cry * (g.n_cry + 1) / 2;  // c1 <= c2
+  for (long long p0 = 0; p0 < npz; p0 += (1LL << 24)) {
+    const long long m = std::min(1LL << 24, npz - p0);
+    hipLaunchKernelGGL(k_sens_zdom, dim3((unsigned)m), dim3(kLanes), 0, st, g, p0, m, img);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  done = true;
+  return LM_OK;
+}
+
+}  // namespace lmk

@@ -311,6 +311,9 @@ int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long
 }
 
 int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
+  bool done = false;
+  if (int rc = launch_sens_lines(g, img, st, done)) return rc;
+  if (done) return LM_OK;
   const long long nd = g.n_det;
   const long long npairs = nd * (nd - 1) / 2;
   const long long chunk = chunk_items(64);
