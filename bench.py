@@ -79,7 +79,7 @@ KERNEL_SOURCES = {
     "tv": ["lm_image.hip", "lm_device.hpp"],
     "primal": ["lm_image.hip"],
     "fwd": ["lm_project.hip", "lm_device.hpp"],
-    "back": ["lm_project.hip", "lm_device.hpp"],
+    "back": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip"],
 }
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and

@@ -95,14 +95,22 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
 
 /* Listmode back projection, the adjoint of lm_fwd: img += (P^LM)^T v.  It
  * ACCUMULATES (FP32 atomics, so the summation order is not fixed); the
- * caller zeroes img.  v: float[n]. */
+ * caller zeroes img.  v: float[n].  Events that are out of range or have
+ * v = 0 contribute nothing.  On a cylindrical scanner (crystal c of ring r
+ * at (x_c, y_c, z_r), z increasing with r) a list of at least 64 events per
+ * transaxial crystal pair is back projected by transaxial line after a
+ * counting sort on the device: 16 more bytes per event of stream-ordered
+ * temporary memory, and one host synchronisation of `stream` (the crystal
+ * table is read back to check the scanner's shape). */
 int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img,
             void *stream);
 
 /* Sensitivity image g += P^T 1 over every unordered crystal pair and every
  * TOF bin (the back projection of a sinogram of ones that Algorithm 2's
  * initialisation and the step sizes T need; Section 2, after Eq.
- * lm_stepsizes).  Accumulates into g; the caller zeroes it. */
+ * lm_stepsizes).  Accumulates into g; the caller zeroes it.  On a
+ * cylindrical 3D scanner (as for lm_back) the pairs are taken by transaxial
+ * line, which synchronises `stream` once to check the scanner's shape. */
 int lm_sens(const lm_geom *G, float *g, void *stream);
 
 /* Synchronous: count events whose crystal, ring or TOF index is out of

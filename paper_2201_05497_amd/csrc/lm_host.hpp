@@ -86,6 +86,10 @@ int launch_sens(const GeomDev &g, float *img, hipStream_t st);
 // Sensitivity by transaxial line (lm_lines.hip) for cylindrical 3D
 // scanners; `done` is false when the geometry does not qualify.
 int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done);
+// Back projection of a long event list by transaxial line (lm_lines.hip);
+// `done` is false when the geometry or the list does not qualify.
+int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st,
+                      bool &done);
 // Plan-internal event records: int4 {id1, id2, k, s bits}.
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
                    hipStream_t st);

@@ -312,6 +312,172 @@ __global__ __launch_bounds__(kLanes) void k_sens_zdom(GeomDev g, long long p0, l
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Back projection of a long event list by line: the events are counted and
+// placed per line (a counting sort on the GPU), then one wavefront per
+// (line, chunk, z part) accumulates its line's events as the sensitivity
+// kernel does its ring pairs.  Events whose dominant axis is z take the
+// per-event projector.
+
+// An event on a line in the line's orientation (crystal c1 < c2): rings and
+// TOF bin packed as r1 | r2 << 12 | (k + kmax) << 24, and its value.
+struct LineRec {
+  unsigned rk;
+  float v;
+};
+
+// Line of a caller event, or -1 when it takes no part in the line pass
+// (out of range, zero value, both ends on one transaxial crystal, or a z
+// dominant axis); rk as in LineRec.
+__device__ __forceinline__ int event_line(const GeomDev &g, const int16_t *e, float v, unsigned &rk) {
+  int id1, id2, k;
+  if (!decode_event(g, e, id1, id2, k) || v == 0.0f) return -1;
+  int c1 = e[0], r1 = e[1], c2 = e[2], r2 = e[3];
+  if (c1 == c2) return -1;
+  if (c1 > c2) {  // the line's orientation: swap the ends, mirror the TOF bin
+    const int tc = c1, tr = r1;
+    c1 = c2;
+    r1 = r2;
+    c2 = tc;
+    r2 = tr;
+    k = -k;
+  }
+  const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
+  const float dz = g.det[3 * (g.n_cry * r2) + 2] - g.det[3 * (g.n_cry * r1) + 2];
+  if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], dz) == 2) return -1;
+  rk = (unsigned)r1 | ((unsigned)r2 << 12) | ((unsigned)(k + g.kmax) << 24);
+  const long long n = g.n_cry;
+  return (int)(c1 * n - (long long)c1 * (c1 + 1) / 2 + (c2 - c1 - 1));
+}
+
+// Line of every event and its rank among its line's events (in no fixed
+// order: the rank comes from an atomic counter per line).
+__global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int16_t *ev, const float *v, long long n,
+                                                   int *key, unsigned *rank, unsigned *cnt) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  unsigned rk;
+  const int L = event_line(g, ev + 5 * e, v[e], rk);
+  key[e] = L;
+  if (L >= 0) rank[e] = atomicAdd(cnt + L, 1u);
+}
+
+// Exclusive prefix sum of cnt[0 .. n) into off[0 .. n]; one block of 1024
+// threads, each summing a contiguous segment.
+__global__ __launch_bounds__(1024) void k_line_offsets(const unsigned *cnt, long long n, unsigned *off) {
+  __shared__ unsigned part[1024];
+  const int t = threadIdx.x;
+  const long long seg = (n + 1023) / 1024;
+  const long long a = min(n, t * seg), b = min(n, a + seg);
+  unsigned sum = 0;
+  for (long long i = a; i < b; ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the segment sums
+    const unsigned add = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  unsigned run = part[t] - sum;
+  for (long long i = a; i < b; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int16_t *ev, const float *v, long long n,
+                                                    const int *key, const unsigned *rank, const unsigned *off,
+                                                    LineRec *rec) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int L = key[e];
+  if (L < 0) return;
+  unsigned rk;
+  event_line(g, ev + 5 * e, v[e], rk);
+  LineRec r;
+  r.rk = rk;
+  r.v = v[e];
+  rec[off[L] + rank[e]] = r;
+}
+
+// Back projection of the events of every line (records rec[off[L] ..
+// off[L+1])); blocks as in k_sens_lines.  An event is skipped on uniform
+// values when its TOF window or its z range misses the chunk and part.
+__global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned *off, const LineRec *rec,
+                                                       long long p0, long long nlines, int nchunk, int nzp,
+                                                       float *img) {
+  __shared__ float acc[2 * kZPart * kLanes];
+  const long long blk = (long long)blockIdx.x;
+  const long long per_line = (long long)nchunk * nzp;
+  if (blk / per_line >= nlines) return;
+  const long long p = p0 + blk / per_line;
+  const unsigned e0 = off[p], e1 = off[p + 1];
+  if (e0 == e1) return;
+  const int chunk = (int)((blk / nzp) % nchunk), part = (int)(blk % nzp);
+  const int lane = threadIdx.x;
+  const int nz = g.n[2];
+  ZPart zp;
+  zp.zlo = part * kZPart;
+  zp.zc = min(kZPart, nz - zp.zlo);
+  int c1, c2;
+  pair_of(p, g.n_cry, c1, c2);
+  const LineLane q = line_lane(g, c1, c2, chunk * kLanes, lane);
+  const unsigned long long act = __ballot(q.active);
+  if (act == 0) return;
+  const int la = __ffsll((long long)act) - 1, lb = 63 - __clzll((long long)act);
+  const double lam_a = __shfl(q.lam, la), lam_b = __shfl(q.lam, lb);
+  for (int i = lane; i < 2 * zp.zc * kLanes; i += kLanes) acc[i] = 0.0f;
+  const double edge = 0.5 * g.tof_bin;
+  const float wfull = tof_weight(g.vclip, -g.vclip, g.vclip, g.inv_norm);
+  const double ihz = 1.0 / g.h[2];
+  for (unsigned e = e0; e < e1; ++e) {
+    const LineRec r = rec[e];
+    const int r1 = (int)(r.rk & 4095u), r2 = (int)((r.rk >> 12) & 4095u), k = (int)(r.rk >> 24) - g.kmax;
+    const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
+    Lor o;
+    lor_z(g, ihz, z1f, z2f, o);
+    const double ua = fma(lam_a, o.bz, o.az), ub = fma(lam_b, o.bz, o.az);
+    if (floor(fmax(ua, ub)) + 2.0 < (double)zp.zlo || floor(fmin(ua, ub)) - 1.0 >= (double)(zp.zlo + zp.zc))
+      continue;  // z range outside the part (one voxel of margin)
+    lor_rest(g, q, z1f, z2f, k * g.tof_bin, edge, r.v, o);
+    if (g.tof_on) {
+      // vh decreases along the line: every sample of the chunk lies beyond
+      // one edge of the bin's truncated window (a margin for rounding)
+      const double vh_a = o.A - lam_a * o.B, vh_b = o.A - lam_b * o.B;
+      if (fmin(vh_a, vh_b) - o.D >= g.vclip + 1e-3 || fmax(vh_a, vh_b) <= -g.vclip - 1e-3) continue;
+    }
+    add_lor(g, q, o, zp, wfull, acc, nz, lane);
+  }
+  flush(g, q, zp, acc, img, lane);
+}
+
+// The events the line pass leaves to the per-event projector: those whose
+// dominant axis is z (one event per wavefront, as the plain back projection).
+__global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const float *v, const int16_t *ev, long long n,
+                                                   float *img) {
+  __shared__ Stage1 st[4];
+  const int lane = threadIdx.x % kLanes, wv = threadIdx.x / kLanes;
+  const long long e = (long long)blockIdx.x * 4 + wv;
+  if (e >= n) return;
+  const float ve = v[e];
+  int id1, id2, k;
+  if (ve == 0.0f || !decode_event(g, ev + 5 * e, id1, id2, k)) return;
+  const float *d1 = g.det + 3 * id1, *d2 = g.det + 3 * id2;
+  if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], d2[2] - d1[2]) != 2) return;
+  const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
+  const float c = r.L * ve;
+  const int o = brick_offset(g.lay, r);
+  for (int j0 = -o; j0 < r.nplanes; j0 += kLanes) {
+    const int j = j0 + lane;
+    Sample s = sample_at(g, r, j, g.tof_on);
+    const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
+    scatter_interleaved(g, img, r, s, cs, lane, st[wv].idx, st[wv].val);
+  }
+}
+
 }  // namespace
 
 namespace lmk {
@@ -364,6 +530,69 @@ int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done) 
     hipLaunchKernelGGL(k_sens_zdom, dim3((unsigned)m), dim3(kLanes), 0, st, g, p0, m, img);
     LM_TRY_HIP(hipGetLastError());
   }
+  done = true;
+  return LM_OK;
+}
+
+
+// Back projection of a long list by line: worth it when the lines carry
+// many events each (the per-block flush costs about as many atomics as
+// a few tens of events do on the per-event path).
+constexpr long long kMinEventsPerLine = 64;
+
+int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st,
+                      bool &done) {
+  done = false;
+  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
+  if (g.n_ring < 2 || g.n_cry < 2 || g.n_ring > 4096 || g.n_tof > 255) return LM_OK;
+  if (n < kMinEventsPerLine * nlines || n >= (1LL << 31) || nlines >= (1LL << 31)) return LM_OK;
+  bool cyl = false;
+  if (int rc = cylindrical(g, st, cyl)) return rc;
+  if (!cyl) return LM_OK;
+  int *key = nullptr;
+  unsigned *rank = nullptr, *cnt = nullptr, *off = nullptr;
+  LineRec *rec = nullptr;
+  hipError_t e = hipMallocAsync((void **)&key, n * sizeof(int), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&rank, n * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, nlines * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&off, (nlines + 1) * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&rec, n * sizeof(LineRec), st);
+  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, nlines * sizeof(unsigned), st);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_line_keys, dim3(grid), dim3(256), 0, st, g, ev, v, n, key, rank, cnt);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, cnt, nlines, off);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_line_place, dim3(grid), dim3(256), 0, st, g, ev, v, n, key, rank, off, rec);
+    e = hipGetLastError();
+  }
+  const int na_max = std::max(g.n[0], g.n[1]);
+  const int nchunk = (na_max + kLanes - 1) / kLanes;
+  const int nzp = (g.n[2] + kZPart - 1) / kZPart;
+  const long long per = std::max<long long>(1, (1LL << 24) / ((long long)nchunk * nzp));
+  for (long long p0 = 0; e == hipSuccess && p0 < nlines; p0 += per) {
+    const long long m = std::min(per, nlines - p0);
+    hipLaunchKernelGGL(k_back_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, off, rec, p0, m,
+                       nchunk, nzp, img);
+    e = hipGetLastError();
+  }
+  for (long long o = 0; e == hipSuccess && o < n; o += (1LL << 22) * 4) {
+    const long long m = std::min((1LL << 22) * 4, n - o);
+    hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, g, v + o, ev + 5 * o, m, img);
+    e = hipGetLastError();
+  }
+  // release errors are not reported
+  if (key) (void)hipFreeAsync(key, st);
+  if (rank) (void)hipFreeAsync(rank, st);
+  if (cnt) (void)hipFreeAsync(cnt, st);
+  if (off) (void)hipFreeAsync(off, st);
+  if (rec) (void)hipFreeAsync(rec, st);
+  LM_TRY_HIP(e);
   done = true;
   return LM_OK;
 }

@@ -301,6 +301,9 @@ int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n,
   return fwd_impl(g, x, CallerEvents{ev}, n, out, st);
 }
 int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st) {
+  bool done = false;
+  if (int rc = launch_back_lines(g, v, ev, n, img, st, done)) return rc;
+  if (done) return LM_OK;
   return back_impl(g, v, CallerEvents{ev}, n, img, st);
 }
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out, hipStream_t st) {

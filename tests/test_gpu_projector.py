@@ -188,6 +188,30 @@ def test_sens_by_line_matches_oracle(P, scanner):
     assert e <= BACK_TOL
 
 
+def test_back_by_line_matches_oracle(P):
+    """A list with many events per transaxial line (here 150 on each of the
+    276 lines of a 24-crystal, 36-ring scanner, two z parts) is back
+    projected by line after a counting sort on the GPU; the events whose
+    dominant axis is z, both ends on one crystal column, the same crystal
+    twice, zero values and both orientations of a line are included."""
+    p = lmsynth.tiny_3d(n_cry=24, n_ring=36, nxy=12, nz=36, h=2.6, radius=30.0, pitch=2.6, n_tof=9,
+                        tof_bin=12.0, fwhm=30.0)
+    ev = lmsynth.random_events(p, 41400, seed=31, min_sep=1)
+    rng = np.random.default_rng(32)
+    axial = np.stack([np.full(200, 5), rng.integers(0, 36, 200), np.full(200, 5), rng.integers(0, 36, 200),
+                      rng.integers(-4, 5, 200)], axis=1).astype(np.int16)
+    ev = np.concatenate([ev, axial])
+    v = rng.uniform(-1, 1, len(ev)).astype(np.float32)
+    v[::97] = 0.0
+    Gg, Go = _pair(P, p)
+    assert len(ev) >= 64 * (24 * 23 // 2)  # the line path's threshold
+    _back_check(P, Gg, Go, v, ev, "3d back by line")
+    # the same list split below the threshold takes the per-event path
+    half = P.lm_back(Gg, torch.as_tensor(v[:8000], device="cuda"), Gg.events(ev[:8000]))
+    _back_check(P, Gg, Go, v[:8000], ev[:8000], "3d back per event")
+    assert torch.isfinite(half).all()
+
+
 def test_large_image_planes_bound(P):
     """A non-TOF projection across the largest supported image uses the
     widest lane configuration and still matches the oracle."""
