@@ -403,6 +403,14 @@ __global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int16_t *ev
   rec[off[L] + rank[e]] = r;
 }
 
+// Lane j's value of x (j uniform).
+__device__ __forceinline__ double readlane_f64(double x, int j) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Back projection of the events of every line (records rec[off[L] ..
 // off[L+1])); blocks as in k_sens_lines.  An event is skipped on uniform
 // values when its TOF window or its z range misses the chunk and part.
@@ -433,23 +441,48 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned
   const double edge = 0.5 * g.tof_bin;
   const float wfull = tof_weight(g.vclip, -g.vclip, g.vclip, g.inv_norm);
   const double ihz = 1.0 / g.h[2];
-  for (unsigned e = e0; e < e1; ++e) {
-    const LineRec r = rec[e];
-    const int r1 = (int)(r.rk & 4095u), r2 = (int)((r.rk >> 12) & 4095u), k = (int)(r.rk >> 24) - g.kmax;
-    const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
+  // 64 events at a time: each lane loads one event and tests it (z range,
+  // TOF window) for this chunk and part, then the wavefront adds the events
+  // that pass, one after the other, with their coefficients broadcast.
+  for (unsigned b0 = e0; b0 < e1; b0 += kLanes) {
+    const unsigned e = b0 + lane;
+    bool pass = false;
     Lor o;
-    lor_z(g, ihz, z1f, z2f, o);
-    const double ua = fma(lam_a, o.bz, o.az), ub = fma(lam_b, o.bz, o.az);
-    if (floor(fmax(ua, ub)) + 2.0 < (double)zp.zlo || floor(fmin(ua, ub)) - 1.0 >= (double)(zp.zlo + zp.zc))
-      continue;  // z range outside the part (one voxel of margin)
-    lor_rest(g, q, z1f, z2f, k * g.tof_bin, edge, r.v, o);
-    if (g.tof_on) {
-      // vh decreases along the line: every sample of the chunk lies beyond
-      // one edge of the bin's truncated window (a margin for rounding)
-      const double vh_a = o.A - lam_a * o.B, vh_b = o.A - lam_b * o.B;
-      if (fmin(vh_a, vh_b) - o.D >= g.vclip + 1e-3 || fmax(vh_a, vh_b) <= -g.vclip - 1e-3) continue;
+    o.A = o.B = o.az = o.bz = 0.0;
+    o.D = o.c = 0.0f;
+    if (e < e1) {
+      const LineRec r = rec[e];
+      const int r1 = (int)(r.rk & 4095u), r2 = (int)((r.rk >> 12) & 4095u), k = (int)(r.rk >> 24) - g.kmax;
+      const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
+      lor_z(g, ihz, z1f, z2f, o);
+      const double ua = fma(lam_a, o.bz, o.az), ub = fma(lam_b, o.bz, o.az);
+      // z range inside the part (one voxel of margin)
+      pass = !(floor(fmax(ua, ub)) + 2.0 < (double)zp.zlo ||
+               floor(fmin(ua, ub)) - 1.0 >= (double)(zp.zlo + zp.zc));
+      if (pass) {
+        lor_rest(g, q, z1f, z2f, k * g.tof_bin, edge, r.v, o);
+        if (g.tof_on) {
+          // vh decreases along the line: every sample of the chunk lies
+          // beyond one edge of the bin's truncated window (a margin for
+          // rounding)
+          const double vh_a = o.A - lam_a * o.B, vh_b = o.A - lam_b * o.B;
+          if (fmin(vh_a, vh_b) - o.D >= g.vclip + 1e-3 || fmax(vh_a, vh_b) <= -g.vclip - 1e-3) pass = false;
+        }
+      }
     }
-    add_lor(g, q, o, zp, wfull, acc, nz, lane);
+    unsigned long long m = __ballot(pass);
+    while (m) {
+      const int j = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      Lor oj;
+      oj.A = readlane_f64(o.A, j);
+      oj.B = readlane_f64(o.B, j);
+      oj.az = readlane_f64(o.az, j);
+      oj.bz = readlane_f64(o.bz, j);
+      oj.D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.D), j));
+      oj.c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.c), j));
+      add_lor(g, q, oj, zp, wfull, acc, nz, lane);
+    }
   }
   flush(g, q, zp, acc, img, lane);
 }
