@@ -103,8 +103,6 @@ PMC_TRAFFIC: dict = {
 PMC_ATOMICS: dict = {
     "data_update": {"requests_per_event": 47.29, "sources": "b27cdaf7e51c4781",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
-    "back": {"requests_per_event": 66.97, "sources": "b27cdaf7e51c4781",
-        "profile": "profiles/pass_3d_300x300x96_counters.txt"},
 }
 
 # Number of random positions of the atomic-rate calibration.
@@ -619,9 +617,6 @@ def large_leg(args, torch, P, lmsynth):
         kernels = {k: {"us_avg": round(1e3 * ms / c, 2), "timed_launches": c} for k, (ms, c) in timing.items() if c}
 
     roof = roofline("back", BYTES_PER_EVENT_PROJ * N, t_back * 1e3)
-    # lm_back runs as consecutive launches; the requests per event do not
-    # depend on the launch size, so the whole call stands for one launch
-    bind = binding("back", N, t_back * 1e3, calibrate_atomics(torch, dev))
     return {
         "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
         "value": round(value, 1),
@@ -644,7 +639,6 @@ def large_leg(args, torch, P, lmsynth):
                  "back_events_per_s": round(N / (t_back * 1e-3), 1),
                  "algorithmic_GBs": round(2 * BYTES_PER_EVENT_PROJ * N / (t_pass * 1e-3) / 1e9, 1)},
         "roofline": roof,
-        "binding": bind,
         "kernels": kernels,
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create_init": round(t_plan, 3)},
     }, p

@@ -178,6 +178,26 @@ __device__ __forceinline__ void flush(const GeomDev &g, const LineLane &q, const
   }
 }
 
+// Lane j's value of x (j uniform).
+__device__ __forceinline__ double readlane_f64(double x, int j) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lane j's LOR coefficients (j uniform).
+__device__ __forceinline__ Lor broadcast(const Lor &o, int j) {
+  Lor r;
+  r.A = readlane_f64(o.A, j);
+  r.B = readlane_f64(o.B, j);
+  r.az = readlane_f64(o.az, j);
+  r.bz = readlane_f64(o.bz, j);
+  r.D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.D), j));
+  r.c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.c), j));
+  return r;
+}
+
 // z extent of a part: 2 x kZPart x 64 floats of LDS per wavefront.
 constexpr int kZPart = 32;
 
@@ -251,13 +271,26 @@ __global__ __launch_bounds__(kLanes) void k_sens_lines(GeomDev g, long long p0, 
       if (below_hi(mid)) lo = mid + 1; else hi = mid;
     }
     const int r2b = lo;
-    for (int r2 = r2a; r2 < r2b; ++r2) {
-      const float z2f = zring(r2);
-      if (dominant_axis(q.fdx, q.fdy, z2f - z1f) == 2) continue;  // per-LOR path
+    // 64 ring pairs at a time: lane l sets up ring pair r2 = b + l, then
+    // the wavefront adds them one after the other
+    for (int b = r2a; b < r2b; b += kLanes) {
+      const int r2 = b + lane;
+      bool pass = false;
       Lor o;
-      lor_z(g, ihz, z1f, z2f, o);
-      lor_rest(g, q, z1f, z2f, 0.0, edge, 1.0f, o);
-      add_lor(g, q, o, zp, wfull, acc, nz, lane);
+      o.A = o.B = o.az = o.bz = 0.0;
+      o.D = o.c = 0.0f;
+      if (r2 < r2b) {
+        const float z2f = zring(r2);
+        pass = dominant_axis(q.fdx, q.fdy, z2f - z1f) != 2;  // z dominant: per-LOR path
+        lor_z(g, ihz, z1f, z2f, o);
+        lor_rest(g, q, z1f, z2f, 0.0, edge, 1.0f, o);
+      }
+      unsigned long long m = __ballot(pass);
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        add_lor(g, q, broadcast(o, j), zp, wfull, acc, nz, lane);
+      }
     }
   }
   flush(g, q, zp, acc, img, lane);
@@ -403,14 +436,6 @@ __global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int16_t *ev
   rec[off[L] + rank[e]] = r;
 }
 
-// Lane j's value of x (j uniform).
-__device__ __forceinline__ double readlane_f64(double x, int j) {
-  const long long b = __double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Back projection of the events of every line (records rec[off[L] ..
 // off[L+1])); blocks as in k_sens_lines.  An event is skipped on uniform
 // values when its TOF window or its z range misses the chunk and part.
@@ -474,14 +499,7 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned
     while (m) {
       const int j = __ffsll((long long)m) - 1;
       m &= m - 1;
-      Lor oj;
-      oj.A = readlane_f64(o.A, j);
-      oj.B = readlane_f64(o.B, j);
-      oj.az = readlane_f64(o.az, j);
-      oj.bz = readlane_f64(o.bz, j);
-      oj.D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.D), j));
-      oj.c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o.c), j));
-      add_lor(g, q, oj, zp, wfull, acc, nz, lane);
+      add_lor(g, q, broadcast(o, j), zp, wfull, acc, nz, lane);
     }
   }
   flush(g, q, zp, acc, img, lane);
