@@ -87,11 +87,11 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104924533, "write_bytes": 98294799, "sources": "b27cdaf7e51c4781",
+    "data_update": {"fetch_bytes": 104911991, "write_bytes": 98294766, "sources": "5938545011bd2338",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106589979, "write_bytes": 76868807, "sources": "9b6e39d3be0a4650",
+    "tv": {"fetch_bytes": 106566124, "write_bytes": 76866056, "sources": "9b6e39d3be0a4650",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "dual_image": {"fetch_bytes": 61408543, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
+    "dual_image": {"fetch_bytes": 61408650, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
 }
 
@@ -101,7 +101,7 @@ PMC_TRAFFIC: dict = {
 # TCC_EA0_ATOMIC_sum reads the same), with the digest of the kernel's
 # sources at the time.
 PMC_ATOMICS: dict = {
-    "data_update": {"requests_per_event": 47.29, "sources": "b27cdaf7e51c4781",
+    "data_update": {"requests_per_event": 47.29, "sources": "5938545011bd2338",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
 }
 
