@@ -360,14 +360,17 @@ struct LineRec {
   float v;
 };
 
-// Line of a caller event, or -1 when it takes no part in the line pass
-// (out of range, zero value, both ends on one transaxial crystal, or a z
-// dominant axis); rk as in LineRec.
+// Line of a caller event; kPerEvent for an event the per-event projector
+// takes (a z dominant axis, which includes both ends on one transaxial
+// crystal), kNoEvent for one that contributes nothing (out of range, zero
+// value, the same crystal twice).  rk as in LineRec.
+constexpr int kNoEvent = -1, kPerEvent = -2;
+
 __device__ __forceinline__ int event_line(const GeomDev &g, const int16_t *e, float v, unsigned &rk) {
   int id1, id2, k;
-  if (!decode_event(g, e, id1, id2, k) || v == 0.0f) return -1;
+  if (!decode_event(g, e, id1, id2, k) || v == 0.0f) return kNoEvent;
   int c1 = e[0], r1 = e[1], c2 = e[2], r2 = e[3];
-  if (c1 == c2) return -1;
+  if (c1 == c2) return r1 == r2 ? kNoEvent : kPerEvent;
   if (c1 > c2) {  // the line's orientation: swap the ends, mirror the TOF bin
     const int tc = c1, tr = r1;
     c1 = c2;
@@ -378,7 +381,7 @@ __device__ __forceinline__ int event_line(const GeomDev &g, const int16_t *e, fl
   }
   const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
   const float dz = g.det[3 * (g.n_cry * r2) + 2] - g.det[3 * (g.n_cry * r1) + 2];
-  if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], dz) == 2) return -1;
+  if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], dz) == 2) return kPerEvent;
   rk = (unsigned)r1 | ((unsigned)r2 << 12) | ((unsigned)(k + g.kmax) << 24);
   const long long n = g.n_cry;
   return (int)(c1 * n - (long long)c1 * (c1 + 1) / 2 + (c2 - c1 - 1));
@@ -505,27 +508,34 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned
   flush(g, q, zp, acc, img, lane);
 }
 
-// The events the line pass leaves to the per-event projector: those whose
-// dominant axis is z (one event per wavefront, as the plain back projection).
-__global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const float *v, const int16_t *ev, long long n,
-                                                   float *img) {
+// The events the line pass leaves to the per-event projector (key
+// kPerEvent).  Each wavefront reads the keys of 64 events at a time and
+// projects the marked ones one after the other (a whole wavefront per
+// event, as the plain back projection); the grid strides over the list.
+__global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const float *v, const int16_t *ev, const int *key,
+                                                   long long n, float *img) {
   __shared__ Stage1 st[4];
   const int lane = threadIdx.x % kLanes, wv = threadIdx.x / kLanes;
-  const long long e = (long long)blockIdx.x * 4 + wv;
-  if (e >= n) return;
-  const float ve = v[e];
-  int id1, id2, k;
-  if (ve == 0.0f || !decode_event(g, ev + 5 * e, id1, id2, k)) return;
-  const float *d1 = g.det + 3 * id1, *d2 = g.det + 3 * id2;
-  if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], d2[2] - d1[2]) != 2) return;
-  const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
-  const float c = r.L * ve;
-  const int o = brick_offset(g.lay, r);
-  for (int j0 = -o; j0 < r.nplanes; j0 += kLanes) {
-    const int j = j0 + lane;
-    Sample s = sample_at(g, r, j, g.tof_on);
-    const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
-    scatter_interleaved(g, img, r, s, cs, lane, st[wv].idx, st[wv].val);
+  const long long nw = (long long)gridDim.x * 4;
+  for (long long b0 = ((long long)blockIdx.x * 4 + wv) * kLanes; b0 < n; b0 += nw * kLanes) {
+    const long long e = b0 + lane;
+    unsigned long long m = __ballot(e < n && key[e] == kPerEvent);
+    while (m) {
+      const int jl = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long ej = b0 + jl;
+      int id1, id2, k;
+      decode_event(g, ev + 5 * ej, id1, id2, k);  // valid: the key is set only for valid events
+      const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
+      const float c = r.L * v[ej];
+      const int o = brick_offset(g.lay, r);
+      for (int j0 = -o; j0 < r.nplanes; j0 += kLanes) {
+        const int j = j0 + lane;
+        Sample s = sample_at(g, r, j, g.tof_on);
+        const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
+        scatter_interleaved(g, img, r, s, cs, lane, st[wv].idx, st[wv].val);
+      }
+    }
   }
 }
 
@@ -632,9 +642,10 @@ int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long 
                        nchunk, nzp, img);
     e = hipGetLastError();
   }
-  for (long long o = 0; e == hipSuccess && o < n; o += (1LL << 22) * 4) {
-    const long long m = std::min((1LL << 22) * 4, n - o);
-    hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, g, v + o, ev + 5 * o, m, img);
+  if (e == hipSuccess) {
+    // 4096 blocks of 4 wavefronts stride over the list
+    const long long nb = std::min<long long>(4096, (n + 4 * kLanes - 1) / (4 * kLanes));
+    hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)nb), dim3(256), 0, st, g, v, ev, key, n, img);
     e = hipGetLastError();
   }
   // release errors are not reported
