@@ -100,8 +100,9 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
  * at (x_c, y_c, z_r), z increasing with r) a list of at least 64 events per
  * transaxial crystal pair is back projected by transaxial line after a
  * counting sort on the device: 16 more bytes per event of stream-ordered
- * temporary memory, and one host synchronisation of `stream` (the crystal
- * table is read back to check the scanner's shape). */
+ * temporary memory (without room for it the per-event path runs), and one
+ * host synchronisation of `stream` (the crystal table is read back to
+ * check the scanner's shape). */
 int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img,
             void *stream);
 

@@ -613,11 +613,24 @@ int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long 
   int *key = nullptr;
   unsigned *rank = nullptr, *cnt = nullptr, *off = nullptr;
   LineRec *rec = nullptr;
+  auto release = [&]() {  // release errors are not reported
+    if (key) (void)hipFreeAsync(key, st);
+    if (rank) (void)hipFreeAsync(rank, st);
+    if (cnt) (void)hipFreeAsync(cnt, st);
+    if (off) (void)hipFreeAsync(off, st);
+    if (rec) (void)hipFreeAsync(rec, st);
+  };
   hipError_t e = hipMallocAsync((void **)&key, n * sizeof(int), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&rank, n * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, nlines * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&off, (nlines + 1) * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&rec, n * sizeof(LineRec), st);
+  if (e == hipErrorOutOfMemory) {
+    // no room for the sort: the per-event path needs no temporaries
+    release();
+    (void)hipGetLastError();
+    return LM_OK;
+  }
   if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, nlines * sizeof(unsigned), st);
   const unsigned grid = (unsigned)((n + 255) / 256);
   if (e == hipSuccess) {
@@ -648,12 +661,7 @@ int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long 
     hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)nb), dim3(256), 0, st, g, v, ev, key, n, img);
     e = hipGetLastError();
   }
-  // release errors are not reported
-  if (key) (void)hipFreeAsync(key, st);
-  if (rank) (void)hipFreeAsync(rank, st);
-  if (cnt) (void)hipFreeAsync(cnt, st);
-  if (off) (void)hipFreeAsync(off, st);
-  if (rec) (void)hipFreeAsync(rec, st);
+  release();
   LM_TRY_HIP(e);
   done = true;
   return LM_OK;
