@@ -1,18 +1,19 @@
 // Back projection organised by transaxial line, for cylindrical scanners
-// (crystal c of ring r at (x_c, y_c, z_r)): the sensitivity image P^T 1.
+// (crystal c of ring r at (x_c, y_c, z_r)): the sensitivity image P^T 1,
+// and lm_back of long event lists after a counting sort by line.
 //
 // Every line of response between crystals c1 != c2 of any two rings has the
 // same transaxial projection, so when its dominant axis is transaxial it
 // meets the image planes at the same transaxial positions: only its z
 // coordinate, its length and its TOF window depend on the rings.  A
-// wavefront owns one transaxial line and 64 consecutive planes (lane l:
-// plane M0 + l) and accumulates the contributions of all LORs on that line
-// into LDS columns acc[corner][z][lane] (the two transaxial corners of the
-// lane's plane, every z), each lane only touching its own column.  The
-// columns are added to the image once per wavefront, so the image sees one
-// atomic per touched voxel and line instead of one per LOR and voxel.  LORs
-// whose dominant axis is z (short transaxial chords, large ring
-// differences) keep the per-LOR projector.
+// wavefront owns one transaxial line, 64 consecutive planes (lane l: plane
+// M0 + l) and a part of 32 z planes, and accumulates the contributions of
+// the line's LORs into LDS columns acc[corner][z][lane] (the two transaxial
+// corners of the lane's plane over the part), each lane only touching its
+// own column.  The columns are added to the image once per wavefront, so
+// the image sees one atomic per touched voxel and line instead of one per
+// LOR and voxel.  LORs whose dominant axis is z (short transaxial chords,
+// large ring differences) keep the per-LOR projector.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
