@@ -188,7 +188,8 @@ def test_sens_by_line_matches_oracle(P, scanner):
     assert e <= BACK_TOL
 
 
-def test_back_by_line_matches_oracle(P):
+@pytest.mark.parametrize("tof", [True, False])
+def test_back_by_line_matches_oracle(P, tof):
     """A list with many events per transaxial line (here 150 on each of the
     276 lines of a 24-crystal, 36-ring scanner, two z parts) is back
     projected by line after a counting sort on the GPU; the events whose
@@ -203,13 +204,11 @@ def test_back_by_line_matches_oracle(P):
     ev = np.concatenate([ev, axial])
     v = rng.uniform(-1, 1, len(ev)).astype(np.float32)
     v[::97] = 0.0
-    Gg, Go = _pair(P, p)
+    Gg, Go = _pair(P, p, tof_on=tof)
     assert len(ev) >= 64 * (24 * 23 // 2)  # the line path's threshold
-    _back_check(P, Gg, Go, v, ev, "3d back by line")
-    # the same list split below the threshold takes the per-event path
-    half = P.lm_back(Gg, torch.as_tensor(v[:8000], device="cuda"), Gg.events(ev[:8000]))
-    _back_check(P, Gg, Go, v[:8000], ev[:8000], "3d back per event")
-    assert torch.isfinite(half).all()
+    _back_check(P, Gg, Go, v, ev, f"3d back by line tof={tof}")
+    # the start of the list, below the threshold, takes the per-event path
+    _back_check(P, Gg, Go, v[:8000], ev[:8000], f"3d back per event tof={tof}")
 
 
 def test_non_cylindrical_scanner_takes_per_lor_paths(P):
