@@ -87,9 +87,9 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104911991, "write_bytes": 98294766, "sources": "5938545011bd2338",
+    "data_update": {"fetch_bytes": 104902058, "write_bytes": 98294700, "sources": "5938545011bd2338",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106566124, "write_bytes": 76866056, "sources": "9b6e39d3be0a4650",
+    "tv": {"fetch_bytes": 106291905, "write_bytes": 76854145, "sources": "9b6e39d3be0a4650",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     "dual_image": {"fetch_bytes": 61408650, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
