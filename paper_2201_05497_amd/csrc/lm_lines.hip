@@ -201,9 +201,9 @@ __device__ __forceinline__ Lor broadcast(const Lor &o, int j) {
 
 // z extent of a part: 2 x kZPart x 64 floats (8 KB) of LDS per wavefront,
 // which allows 20 wavefronts per CU.  Measured on 5e8 events: parts of 8,
-// 12, 16 and 32 planes took 439, 638, 364 and 438 ms (smaller parts test and add
-// each event in more blocks, larger ones leave fewer wavefronts to hide
-// the latency of each event's LDS updates).
+// 12, 16 and 32 planes took 439, 638, 364 and 438 ms (smaller parts test
+// and add each event in more blocks, larger ones leave fewer wavefronts to
+// hide the latency of each event's LDS updates).
 constexpr int kZPart = 16;
 
 // Sensitivity over the LORs of every line c1 < c2 whose dominant axis is
