@@ -13,22 +13,25 @@ every 8th launch of each kernel class on its own stream, inside the timed
 region.
 
 It prints one JSON line: value = events forward- and back-projected per
-second over the timed epochs, the roofline of the dominant kernel, the FP64
-oracle timed on a bounded sample of the same workload on the host
-(cpu_baseline), seconds per epoch of the 2D workload (1e5 events, 128x128,
-28 subsets), the time of one LMProject forward + backward of the Poisson
-likelihood over 16 frames of 1e6 events and, unless --no-serve, the serving
-measurement: 64
-dynamic-frame requests (event counts log-uniform in 1e5..5e7, half on a
-128x128x48 grid and half on the 200x200x96 one, 28 subsets, 3 epochs each)
-arriving as a Poisson stream at 0.7 of the sequential solver's throughput,
-served by the continuous-batching Server, with p50/p99 latency and events/s
-next to the one-frame-at-a-time solver on the same arrivals, and the same
-64 requests submitted at once (burst makespan against the solver's total).
+second over the timed epochs, the roofline of the dominant kernel (the
+fused data update, on its algorithmic bytes) and its binding resource (its
+FP32 atomic requests per second against a ceiling calibrated in the same
+run), the FP64 oracle timed on a bounded sample of the same workload on the
+host (cpu_baseline), seconds per epoch of the 2D workload (1e5 events,
+128x128, 28 subsets), the time of one LMProject forward + backward of the
+Poisson likelihood over 16 frames of 1e6 events and, unless --no-serve, the
+serving measurement: 64 dynamic-frame requests (event counts log-uniform in
+1e5..5e7, half on a 128x128x48 grid and half on the 200x200x96 one, 28
+subsets, 3 epochs each) arriving as a Poisson stream at 0.7 of the
+sequential solver's throughput, served by the continuous-batching Server,
+with p50/p99 latency and events/s next to the one-frame-at-a-time solver on
+the same arrivals, and the same 64 requests submitted at once (burst
+makespan against the solver's total).
 
 ``--workload large``: the same scanner with a 300x300x96 image of 1.75 x
-1.75 x 2.6 mm voxels and 5e8 events: one lm_fwd + lm_back pass over all
-events per step, then one LM-SPDHG epoch.
+1.75 x 2.6 mm voxels and 5e8 events presented sorted by dominant axis: one
+lm_fwd + lm_back pass over all events per step (lm_back takes its
+by-line path for such a list), then one LM-SPDHG epoch.
 """
 from __future__ import annotations
 
