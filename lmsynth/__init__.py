@@ -602,6 +602,35 @@ def random_events(p: Problem, n: int, seed: int, min_sep: int = 1) -> np.ndarray
     return np.ascontiguousarray(np.stack([c1, r1, c2, r2, k], axis=1).astype(np.int16))
 
 
+def random_events_many(p: Problem, n: int, seed: int, chunk: int = 1 << 23, workers: int = 8) -> np.ndarray:
+    """Uniformly random events (two distinct crystals, any rings, any TOF
+    bin) for lists of 1e8 events and more: int16 draws straight into the
+    output, in chunks seeded from `seed` by SeedSequence.spawn and filled by
+    a pool of threads, so the result does not depend on `workers`."""
+    from concurrent.futures import ThreadPoolExecutor
+    sc, kmax = p.scanner, p.tof.kmax
+    out = np.empty((n, 5), dtype=np.int16)
+    seeds = np.random.SeedSequence(seed).spawn((n + chunk - 1) // chunk)
+
+    def fill(i):
+        o = i * chunk
+        m = min(chunk, n - o)
+        rng = np.random.default_rng(seeds[i])
+        e = out[o:o + m]
+        c1 = rng.integers(0, sc.n_cry, m, dtype=np.int16)
+        c2 = c1.astype(np.int32) + rng.integers(1, sc.n_cry, m, dtype=np.int16)
+        c2[c2 >= sc.n_cry] -= sc.n_cry
+        e[:, 0] = c1
+        e[:, 2] = c2
+        e[:, 1] = rng.integers(0, sc.n_ring, m, dtype=np.int16)
+        e[:, 3] = rng.integers(0, sc.n_ring, m, dtype=np.int16)
+        e[:, 4] = rng.integers(-kmax, kmax + 1, m, dtype=np.int16)
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        list(ex.map(fill, range(len(seeds))))
+    return out
+
+
 # --------------------------------------------------------------------------
 # subset sequence (SplitMix64, Steele, Lea & Flood, OOPSLA 2014)
 

@@ -241,31 +241,41 @@ def test_large_image_planes_bound(P):
 
 
 def test_chunked_launches(P):
-    """Inputs larger than one launch (2^22 blocks): the events around every
-    chunk boundary match the oracle, and the back projection of the whole
-    list equals the sum over its halves."""
+    """Inputs larger than one launch (2^22 blocks): on a list of two lm_fwd
+    launches (32 events per block) and sixteen per-event lm_back launches (4
+    events per block) plus a ragged tail, the events around every launch
+    boundary match the oracle in projection, and in back projection with
+    values that are zero except around the boundaries.  One crystal of the
+    table is moved by 0.05 mm, so that lm_back takes its per-event kernel
+    and not the path by transaxial line."""
     p = problem_3d(1_000_000)
-    Gg, Go = _pair(P, p)
-    lanes = 32  # events per block = 256 / lanes
-    chunk = (1 << 22) * (256 // lanes)
-    n = 2 * chunk + 123
-    base = p.events
-    ev = np.resize(base, (n, 5))
+    sc, tof = p.scanner, p.tof
+    det = p.det.copy()
+    det[100 + sc.n_cry * 40, 0] += 0.05
+    args = (det, sc.n_cry, sc.n_ring, p.image.n, p.image.h, tof.n_tof, tof.bin, tof.fwhm, tof.nsigma, True)
+    Gg, Go = P.Geometry(*args, device="cuda"), oracle.Geometry(*args)
+    fwd_launch, back_launch = (1 << 22) * 32, (1 << 22) * 4
+    n = 2 * fwd_launch + 123
+    ev = np.resize(p.events, (n, 5))
     x = smooth_image(Go.shape, 14, base=float(p.x0.max()))
     evt = Gg.events(ev)
-    got = P.lm_fwd(Gg, torch.as_tensor(x, device="cuda"), evt).cpu().numpy()
-    idx = np.concatenate([np.arange(c - 50, c + 50) for c in (chunk, 2 * chunk)] + [np.arange(n - 50, n)])
-    emax, _ = proj_err(got[idx], oracle.fwd(Go, x, ev[idx]))
+
+    def around(step):
+        return np.concatenate([np.arange(c - 50, c + 50) for c in range(step, n, step)] + [np.arange(n - 50, n)])
+
+    out = P.lm_fwd(Gg, torch.as_tensor(x, device="cuda"), evt)
+    idx = around(fwd_launch)
+    emax, _ = proj_err(out[torch.as_tensor(idx, device="cuda")].cpu().numpy(), oracle.fwd(Go, x, ev[idx]))
+    del out
     report("chunk boundaries fwd", events=n, max_err=emax)
     assert emax <= PROJ_TOL
-    v = torch.full((n,), 0.5, device="cuda")
-    whole = P.lm_back(Gg, v, evt)
-    half = n // 2
-    parts = P.lm_back(Gg, v[:half].contiguous(), evt[:half].contiguous())
-    P.lm_back(Gg, v[half:].contiguous(), evt[half:].contiguous(), parts)
-    e = img_err(whole.cpu().numpy(), parts.cpu().numpy().astype(np.float64))
-    report("chunked back vs halves", err=e)
-    # both sides are FP32 atomic sums (~4e3 per voxel) in different orders
+    jdx = around(back_launch)
+    vals = np.random.default_rng(15).uniform(0.1, 1, len(jdx)).astype(np.float32)
+    v = torch.zeros(n, device="cuda")
+    v[torch.as_tensor(jdx, device="cuda")] = torch.as_tensor(vals, device="cuda")
+    got = P.lm_back(Gg, v, evt).cpu().numpy()
+    e = img_err(got, oracle.back(Go, vals.astype(np.float64), ev[jdx]))
+    report("chunk boundaries back", events=n, nonzero=len(jdx), err=e)
     assert e <= BACK_TOL
 
 

@@ -155,3 +155,23 @@ def test_sort_by_dominant_axis():
         grp = key1[axis == a]
         d0 = np.abs(det[ev0[:, 2] + nc * ev0[:, 3].astype(np.int64)] - det[ev0[:, 0] + nc * ev0[:, 1].astype(np.int64)])
         assert np.array_equal(grp, key0[np.argmax(d0, axis=1) == a])
+
+
+def test_many_random_events_independent_of_workers():
+    """The generator of the long-frame parity lists: the same events for any
+    number of threads, every field in range, two distinct crystals per
+    event, and every crystal, ring and TOF bin drawn."""
+    p = lmsynth.config_3d_large()
+    n = 3 * 200_000 + 17  # a ragged last chunk
+    a = lmsynth.random_events_many(p, n, seed=9, chunk=200_000, workers=1)
+    b = lmsynth.random_events_many(p, n, seed=9, chunk=200_000, workers=3)
+    assert np.array_equal(a, b) and a.dtype == np.int16 and a.shape == (n, 5)
+    sc = p.scanner
+    for col, hi in ((0, sc.n_cry), (2, sc.n_cry), (1, sc.n_ring), (3, sc.n_ring)):
+        assert np.array_equal(np.unique(a[:, col]), np.arange(hi))
+    assert np.array_equal(np.unique(a[:, 4]), np.arange(-p.tof.kmax, p.tof.kmax + 1))
+    assert not np.any(a[:, 0] == a[:, 2])
+    # the transaxial separation is uniform over 1 .. n_cry - 1
+    sep = (a[:, 2].astype(np.int64) - a[:, 0]) % sc.n_cry
+    assert np.array_equal(np.unique(sep), np.arange(1, sc.n_cry))
+    assert not np.array_equal(a, lmsynth.random_events_many(p, n, seed=10, chunk=200_000))
