@@ -9,7 +9,8 @@ float64 and single-threaded, written to be checked against the paper by eye.
 The projector pair lives in ``lm_oracle.c`` (compiled with gcc on first
 use); this module holds the algorithm: event counts, subsets, step sizes,
 the dual proxes, the finite-difference operator K, LM-SPDHG (Algorithm 2),
-sinogram SPDHG on a dense system matrix (Algorithm 1) and the cost (Eq. 1).
+sinogram SPDHG on a dense system matrix (Algorithm 1), the cost (Eq. 1) and
+the listmode EM-TV warm start (Algorithm 3).
 
 Readings of the paper taken here, where it is silent or ambiguous:
 
@@ -457,3 +458,84 @@ def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins
         z = z + dz
         zbar = z + dz / p
     return x.reshape(shape_zyx)
+
+
+# --------------------------------------------------------------------------
+# warm start: listmode EM-TV (Algorithm 3), each subset update an EM step
+# followed by a weighted TV denoising problem solved by the accelerated
+# primal-dual algorithm of Chambolle & Pock (J. Math. Imaging Vis. 40, 2011,
+# their Algorithm 2).
+#
+# Readings taken where the paper is silent:
+# * the EM step's quotient is 1 / (P^LM x + s); an event with P^LM x + s = 0
+#   adds nothing, and z = 0 where g = 0;
+# * w = g / (beta x) is infinite where x = 0: such voxels keep u = z (= 0,
+#   since z is proportional to x); beta = 0 skips the denoising (x = z, OSEM);
+# * subsets are the interleaved ones of LM-SPDHG, visited in the order
+#   0, 1, ..., n-1 in every iteration;
+# * the denoising starts from u = z with a zero dual, tau_0 = sigma_0 =
+#   1/||K||, and takes the uniform convexity constant as the smallest finite
+#   weight.
+
+
+def em_step(geom: Geometry, x: np.ndarray, events, s: np.ndarray, g: np.ndarray, n_subsets: int) -> np.ndarray:
+    """Subset EM step of Algorithm 3 for the events (and s) of one subset:
+    z = x n / g * P^LM^T (1 / (P^LM x + s))."""
+    x = np.asarray(x, dtype=np.float64)
+    q = fwd(geom, x, events) + np.asarray(s, dtype=np.float64)
+    v = np.where(q > 0, 1.0 / np.where(q > 0, q, 1.0), 0.0)
+    bp = back(geom, v, events)
+    return np.where(g > 0, x * n_subsets * bp / np.where(g > 0, g, 1.0), 0.0)
+
+
+def emtv_weights(g: np.ndarray, x: np.ndarray, beta: float) -> np.ndarray:
+    """w = g / (beta x) of Algorithm 3 (inf where x = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(x > 0, g / (beta * np.where(x > 0, x, 1.0)), np.inf)
+
+
+def weighted_tv_denoise(z: np.ndarray, w: np.ndarray, n_iter: int, return_dual: bool = False):
+    """argmin_{u >= 0} sum_j w_j / 2 (u_j - z_j)^2 + ||K u||_{2,1} by n_iter
+    steps of accelerated PDHG: with G(u) the weighted quadratic plus the
+    constraint and F = ||.||_{2,1},
+        q     <- projection of q + sigma K ubar onto the unit balls,
+        u+    <- prox_{tau G}(u - tau K^T q),
+        theta  = 1 / sqrt(1 + 2 gam tau), tau <- theta tau, sigma <- sigma / theta,
+        ubar  <- u+ + theta (u+ - u).
+    prox_{tau G}(v) = max(0, (v + tau w z) / (1 + tau w)), and u = z where w
+    is infinite.  Returns u (and the dual q)."""
+    z = np.asarray(z, dtype=np.float64)
+    fixed = np.isinf(w)
+    wf = np.where(fixed, 0.0, w)
+    gam = float(w[~fixed].min()) if np.any(~fixed) else 0.0
+    tau = sigma = 1.0 / grad_norm(z.shape)
+    u = z.copy()
+    ubar = z.copy()
+    q = np.zeros((3,) + z.shape)
+    for _ in range(n_iter):
+        q = prox_tv_dual(q + sigma * grad(ubar), 1.0)
+        v = u - tau * grad_adjoint(q)
+        up = np.where(fixed, z, np.maximum(0.0, (v + tau * wf * z) / (1.0 + tau * wf)))
+        theta = 1.0 / np.sqrt(1.0 + 2.0 * gam * tau)
+        tau, sigma = theta * tau, sigma / theta
+        ubar = up + theta * (up - u)
+        u = up
+    return (u, q) if return_dual else u
+
+
+def emtv(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarray, n_subsets: int, n_iter: int,
+         beta: float, denoise_iter: int = 20) -> np.ndarray:
+    """Listmode EM-TV (Algorithm 3): n_iter passes over the n_subsets
+    interleaved subsets; each subset update is the EM step, the weights
+    w = g / (beta x) and the weighted TV denoising from the EM image."""
+    ev = _ev(events)
+    s = np.asarray(s, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    sub = subset_ids(len(ev), n_subsets)
+    for _ in range(n_iter):
+        for i in range(n_subsets):
+            m = sub == i
+            z = em_step(geom, x, ev[m], s[m], g, n_subsets)
+            x = z if beta <= 0 else weighted_tv_denoise(z, emtv_weights(g, x, beta), denoise_iter)
+    return x
