@@ -238,6 +238,33 @@ int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
  * safe for concurrent use from several host threads. */
 int lm_plan_destroy(lm_plan *p);
 
+/* ---------------------------------------------------------------- warm start */
+
+/* Listmode EM-TV (Algorithm 3), the warm start of LM-SPDHG: Section 2
+ * (after Eq. yinit) proposes it for x0, and Section 3 runs one iteration
+ * with 28 subsets before every reconstruction, y0 then following from
+ * Eq. yinit (lm_spdhg_init).  n_iter passes over the n_subsets interleaved
+ * subsets (event e in subset e mod n_subsets), visited in the order 0, 1,
+ * ..., n_subsets - 1.  Each subset update computes
+ *   z = x n_subsets / g * P_i^LM^T (1 / (P_i^LM x + s_i))   (EM step; an
+ *       event with P x + s <= 0 adds nothing; z = 0 where g = 0),
+ *   w = g / (beta x)                                        (inf where x = 0),
+ *   x <- argmin_{u >= 0} sum_j w_j / 2 (u_j - z_j)^2 + ||K u||_{2,1},
+ * the last by denoise_iter steps of the accelerated primal-dual algorithm
+ * of Chambolle & Pock (J. Math. Imaging Vis. 40, 2011, Algorithm 2; 20 in
+ * Section 3) from u = z and a zero dual, with tau_0 = sigma_0 = 1/||K||,
+ * the convexity constant equal to the smallest finite w, and u held at z
+ * where w is infinite.  beta = 0 skips the denoising (OSEM).
+ * ev: int16[n][5]; s: float[n] contamination per event; g: sensitivity
+ * image (row-major float[nz][ny][nx], e.g. from lm_sens); x: row-major
+ * float image, x0 >= 0 on entry, the result on return.  All device
+ * pointers, caller-owned.  Asynchronous on stream: temporaries (14 B per
+ * event, 4 B per event of the largest subset, ten images) are allocated
+ * and freed stream-ordered.  LM_EINVAL for bad arguments (nothing run),
+ * LM_ENOMEM when a temporary does not fit. */
+int lm_emtv(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int32_t n_subsets,
+            int32_t n_iter, const float *g, float beta, int32_t denoise_iter, float *x, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

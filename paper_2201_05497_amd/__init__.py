@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LMError
 
 __all__ = ["Geometry", "lm_fwd", "lm_back", "lm_sens", "lm_validate_events", "tv_grad", "tv_div",
-           "lm_plan_bytes", "Plan", "LMError", "exact_grad_norm"]
+           "lm_plan_bytes", "Plan", "lm_emtv", "LMError", "exact_grad_norm"]
 
 _L = _lib.load()
 
@@ -192,6 +192,22 @@ def tv_div(w: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     _need(out, torch.float32, "out", w.device, w[0].numel())
     _lib.check(_L.tv_div(_dims(out), w.data_ptr(), out.data_ptr(), _stream(w.device)), "tv_div")
     return out
+
+
+def lm_emtv(geom: Geometry, ev: torch.Tensor, s: torch.Tensor, g: torch.Tensor, x: torch.Tensor, n_subsets: int,
+            n_iter: int = 1, beta: float = 0.0, denoise_iter: int = 20) -> torch.Tensor:
+    """Listmode EM-TV (Algorithm 3), the warm start of LM-SPDHG: n_iter
+    passes over the n_subsets interleaved subsets, each an EM step and, for
+    beta > 0, a weighted TV denoising by denoise_iter accelerated PDHG
+    steps.  x (x0 >= 0) is updated in place and returned."""
+    n = _ev_check(geom, ev)
+    _need(s, torch.float32, "s", geom.device, n)
+    _need(g, torch.float32, "g", geom.device, geom.nvox)
+    _need(x, torch.float32, "x", geom.device, geom.nvox)
+    _lib.check(_L.lm_emtv(ctypes.byref(geom._c), ev.data_ptr(), s.data_ptr(), n, int(n_subsets), int(n_iter),
+                          g.data_ptr(), float(beta), int(denoise_iter), x.data_ptr(), _stream(geom.device)),
+               "lm_emtv")
+    return x
 
 
 def lm_plan_bytes(geom: Geometry, n_events: int, n_subsets: int) -> int:
