@@ -17,7 +17,10 @@ second over the timed epochs, the roofline of the dominant kernel (the
 fused data update, on its algorithmic bytes) and its binding resource (its
 FP32 atomic requests per second against a ceiling calibrated in the same
 run), the FP64 oracle timed on a bounded sample of the same workload on the
-host (cpu_baseline), seconds per epoch of the 2D workload (1e5 events,
+host (cpu_baseline), the warm start of the same workload (one listmode
+EM-TV iteration, 28 subsets, 20 accelerated PDHG steps per denoising, with
+the time and bandwidth of one denoising step), seconds per epoch of the 2D
+workload (1e5 events,
 128x128, 28 subsets), the time of one LMProject forward + backward of the
 Poisson likelihood over 16 frames of 1e6 events and, unless --no-serve, the
 serving measurement: 64 dynamic-frame requests (event counts log-uniform in
@@ -71,6 +74,12 @@ SERVE_BUDGET = 96 << 30         # HBM bytes the server may hold
 BYTES_PER_VOXEL = {"primal": 16, "dual_image": 28, "tv": 44}
 BYTES_PER_EVENT = 16 + 4 + 4 + 4 + 4
 BYTES_PER_EVENT_PROJ = 10 + 4
+# One accelerated PDHG step of the EM-TV denoising, per voxel: the dual pass
+# reads ubar and q (4 + 12) and writes q (12); the primal pass reads u, z,
+# w and q (4 + 4 + 4 + 12) and writes u and ubar (8).
+BYTES_PER_VOXEL_PD = 28 + 32
+WARM_SUBSETS = 28               # the paper's warm start: 1 EM-TV iteration, 28 subsets,
+WARM_DENOISE = 20               # 20 accelerated PDHG steps per denoising
 
 # Sources that define each kernel class; their digest (code only, comments
 # and whitespace removed) is compared with the one recorded when the HBM
@@ -390,6 +399,46 @@ def epoch_leg(args, torch, P, lmsynth):
     return out, p, G, g
 
 
+# --------------------------------------------------------------------------- warm start
+
+
+def warm_start_leg(torch, P, G, g, p, reps: int = 2):
+    """The warm start of the epoch workload (Algorithm 3): one listmode EM-TV
+    iteration with 28 subsets and 20 accelerated PDHG steps per weighted TV
+    denoising, from the uniform starting image.  Timed once more without
+    denoising steps; the difference, over 28 x 20 steps, gives the time and
+    the bandwidth of one denoising step (dual and primal pass)."""
+    dev = G.device
+    ev = G.events(p.events)
+    s = torch.as_tensor(p.s, device=dev)
+    x0 = torch.as_tensor(p.x0, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(denoise_iter):
+        ts = []
+        for k in range(1 + reps):
+            x = x0.clone()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream)
+            P.lm_emtv(G, ev, s, g, x, WARM_SUBSETS, 1, BETA, denoise_iter)
+            e[1].record(stream)
+            torch.cuda.synchronize()
+            if k:
+                ts.append(e[0].elapsed_time(e[1]))
+        return float(np.mean(ts))
+
+    ms = timed(WARM_DENOISE)
+    ms_em = timed(0)
+    us_step = 1e3 * (ms - ms_em) / (WARM_SUBSETS * WARM_DENOISE)
+    out = {"ms": round(ms, 2), "em_steps_ms": round(ms_em, 2), "subsets": WARM_SUBSETS,
+           "denoise_iter": WARM_DENOISE, "events_per_s": round(len(p.events) / (ms * 1e-3), 1),
+           "denoise_step_us": round(us_step, 2),
+           "denoise_GBs": round(BYTES_PER_VOXEL_PD * G.nvox / (us_step * 1e-6) / 1e9, 1) if us_step > 0 else None}
+    log(f"warm start (EM-TV, {WARM_SUBSETS} subsets): {ms:.1f} ms, EM steps alone {ms_em:.1f} ms, "
+        f"{us_step:.1f} us per denoising step")
+    return out
+
+
 # --------------------------------------------------------------------------- 2D
 
 
@@ -679,6 +728,7 @@ def main() -> int:
             log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
     else:
         out, p, G, g = epoch_leg(args, torch, P, lmsynth)
+        out["warm_start"] = warm_start_leg(torch, P, G, g, p)
         out["epoch_2d"] = leg_2d(torch, P, lmsynth)
         out["autograd"] = autograd_leg(torch, P, lmsynth)
         if not args.no_serve:

@@ -68,13 +68,14 @@ __global__ void k_fill_u32(unsigned *__restrict__ p, long long n, unsigned v) {
 
 // EM image z = x n bp / g (0 where g = 0).  With beta > 0 also the weights
 // w = g / (beta x) (inf where x = 0), the start of the denoising (u = ubar
-// = z, q = 0) and the smallest finite weight (as float bits, atomic min:
-// non-negative floats order like their bits).  With beta = 0, x <- z.
+// = z, q = 0) and the smallest weight of each block in part[blockIdx.x]
+// (as float bits: non-negative floats order like their bits).  With
+// beta = 0, x <- z.
 __global__ __launch_bounds__(kBlock) void k_em_image(float *__restrict__ x, const float *__restrict__ bp,
                                                      const float *__restrict__ g, long long nv, float nsub,
                                                      float beta, float *__restrict__ z, float *__restrict__ w,
                                                      float *__restrict__ u, float *__restrict__ ubar,
-                                                     float *__restrict__ q, unsigned *__restrict__ wmin) {
+                                                     float *__restrict__ q, unsigned *__restrict__ part) {
   __shared__ unsigned red[kBlock / 64];
   unsigned lo = kInfBits;
   for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < nv; j += (long long)gridDim.x * kBlock) {
@@ -100,19 +101,26 @@ __global__ __launch_bounds__(kBlock) void k_em_image(float *__restrict__ x, cons
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < kBlock / 64; ++i) lo = min(lo, red[i]);
-    if (lo < kInfBits) atomicMin(wmin, lo);
+    part[blockIdx.x] = lo;
   }
 }
 
 // Step sizes of the accelerated iterations: tau_0 = sigma_0 = 1/||K||,
 // theta_k = 1 / sqrt(1 + 2 gam tau_k), tau_{k+1} = theta_k tau_k,
 // sigma_{k+1} = sigma_k / theta_k, with gam the smallest finite weight
-// (0 if every weight is infinite or the smallest is 0).  One thread.
-__global__ void k_pd_schedule(const unsigned *__restrict__ wmin, double tau0, int iters,
-                              float4 *__restrict__ sched) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const unsigned b = *wmin;
-  const double gam = b < kInfBits ? (double)__uint_as_float(b) : 0.0;
+// (0 if every weight is infinite or the smallest is 0), reduced here from
+// the npart block minima.  One block of kBlock threads.
+__global__ __launch_bounds__(kBlock) void k_pd_schedule(const unsigned *__restrict__ part, int npart, double tau0,
+                                                        int iters, float4 *__restrict__ sched) {
+  __shared__ unsigned red[kBlock / 64];
+  unsigned lo = kInfBits;
+  for (int i = threadIdx.x; i < npart; i += kBlock) lo = min(lo, part[i]);
+  for (int o = 32; o > 0; o >>= 1) lo = min(lo, (unsigned)__shfl_xor((int)lo, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lo;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = 1; i < kBlock / 64; ++i) lo = min(lo, red[i]);
+  const double gam = lo < kInfBits ? (double)__uint_as_float(lo) : 0.0;
   double tau = tau0, sigma = tau0;
   for (int k = 0; k < iters; ++k) {
     const double theta = 1.0 / sqrt(1.0 + 2.0 * gam * tau);
@@ -126,10 +134,13 @@ __global__ void k_pd_schedule(const unsigned *__restrict__ wmin, double tau0, in
 // each voxel (K = forward differences, zero in the last layer).
 __global__ __launch_bounds__(kBlock) void k_pd_dual(const float *__restrict__ ubar, float *__restrict__ q, int nx,
                                                     int ny, int nz, const float4 *__restrict__ sched, int k) {
-  const long long nxy = (long long)nx * ny, nv = nxy * nz;
+  // images have at most 512^3 voxels: 32-bit indices, also for the three
+  // components of q
+  const unsigned nxy = (unsigned)nx * ny, nv = nxy * nz;
   const float sigma = sched[k].y;
-  for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < nv; j += (long long)gridDim.x * kBlock) {
-    const int ix = (int)(j % nx), iy = (int)((j / nx) % ny), iz = (int)(j / nxy);
+  for (unsigned j = blockIdx.x * kBlock + threadIdx.x; j < nv; j += gridDim.x * kBlock) {
+    const unsigned row = j / nx;
+    const int ix = (int)(j - row * nx), iy = (int)(row % ny), iz = (int)(row / ny);
     const float c = ubar[j];
     const float gx = ix + 1 < nx ? ubar[j + 1] - c : 0.0f;
     const float gy = iy + 1 < ny ? ubar[j + nx] - c : 0.0f;
@@ -150,11 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_pd_primal(const float *u, const floa
                                                       const float *__restrict__ z, const float *__restrict__ w,
                                                       float *u_out, float *__restrict__ ubar, int nx, int ny, int nz,
                                                       const float4 *__restrict__ sched, int k) {
-  const long long nxy = (long long)nx * ny, nv = nxy * nz;
+  const unsigned nxy = (unsigned)nx * ny, nv = nxy * nz;
   const float4 st = sched[k];
   const float tau = st.x, theta = st.z;
-  for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < nv; j += (long long)gridDim.x * kBlock) {
-    const int ix = (int)(j % nx), iy = (int)((j / nx) % ny), iz = (int)(j / nxy);
+  for (unsigned j = blockIdx.x * kBlock + threadIdx.x; j < nv; j += gridDim.x * kBlock) {
+    const unsigned row = j / nx;
+    const int ix = (int)(j - row * nx), iy = (int)(row % ny), iz = (int)(row / ny);
     // (K^T q)_j = sum over axes of q_a[j - e_a] (if j has a lower neighbour)
     // minus q_a[j] (unless j is in the last layer)
     float kt = 0.0f;
@@ -245,7 +257,8 @@ int lm_emtv(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int3
   float *ss = nullptr, *qe = nullptr, *xb = nullptr, *bpb = nullptr, *bp = nullptr;
   float *z = nullptr, *w = nullptr, *u = nullptr, *ubar = nullptr, *q3 = nullptr;
   float4 *sched = nullptr;
-  unsigned *wmin = nullptr;
+  unsigned *part = nullptr;
+  const unsigned img_grid = grid_for(nv);
   if (int rc = t.get(&evs, 5 * n)) return rc;
   if (int rc = t.get(&ss, n)) return rc;
   if (int rc = t.get(&qe, m_max)) return rc;
@@ -258,7 +271,7 @@ int lm_emtv(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int3
     if (int rc = t.get(&u, nv)) return rc;
     if (int rc = t.get(&ubar, nv)) return rc;
     if (int rc = t.get(&q3, 3 * nv)) return rc;
-    if (int rc = t.get(&wmin, 1)) return rc;
+    if (int rc = t.get(&part, img_grid)) return rc;
     if (int rc = t.get(&sched, std::max(iters, 1))) return rc;
   }
   if (n > 0) {
@@ -282,19 +295,15 @@ int lm_emtv(const lm_geom *G, const int16_t *ev, const float *s, int64_t n, int3
         if (int rc = lmk::launch_back(gb, qe, evs + 5 * o, m, bpb, st)) return rc;
       }
       if (int rc = lmk::launch_from_layout(gd.n, gb.lay, 1, bpb, bp, st)) return rc;
-      if (denoise) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, wmin, 1LL, kInfBits);
-        LM_TRY_HIP(hipGetLastError());
-      }
-      hipLaunchKernelGGL(k_em_image, dim3(grid_for(nv)), dim3(kBlock), 0, st, x, bp, g, nv, (float)n_subsets, beta,
-                         z, w, u, ubar, q3, wmin);
+      hipLaunchKernelGGL(k_em_image, dim3(img_grid), dim3(kBlock), 0, st, x, bp, g, nv, (float)n_subsets, beta, z,
+                         w, u, ubar, q3, part);
       LM_TRY_HIP(hipGetLastError());
       if (!denoise) continue;
       if (iters == 0) {
         LM_TRY_HIP(hipMemcpyAsync(x, z, (size_t)nv * sizeof(float), hipMemcpyDeviceToDevice, st));
         continue;
       }
-      hipLaunchKernelGGL(k_pd_schedule, dim3(1), dim3(64), 0, st, wmin, tau0, iters, sched);
+      hipLaunchKernelGGL(k_pd_schedule, dim3(1), dim3(kBlock), 0, st, part, (int)img_grid, tau0, iters, sched);
       LM_TRY_HIP(hipGetLastError());
       for (int k = 0; k < iters; ++k) {
         hipLaunchKernelGGL(k_pd_dual, dim3(grid_for(nv)), dim3(kBlock), 0, st, ubar, q3, gd.n[0], gd.n[1], gd.n[2],
