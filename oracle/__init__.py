@@ -26,7 +26,8 @@ Readings of the paper taken here, where it is silent or ambiguous:
   sign for which z equals P^T of the sinogram dual built from Eq. (yinit)
   (the printed "-" contradicts the sentence that follows the algorithm);
 * K = forward differences with zero (Neumann) boundary, no voxel-size
-  scaling; ||K|| is its exact largest singular value;
+  scaling; ||K|| is its exact largest singular value; for DTV, K = D grad
+  with the full projection D and the same ||grad|| as the norm bound;
 * T = min over the subset step sizes and the prior step size:
   T_j = rho / (2 gamma max(g_j, ||K||)) with p_k = 1/(2n), p_prior = 1/2;
   S_e = gamma rho / (P^LM 1)_e, and 0 where (P^LM 1)_e = 0.
@@ -288,6 +289,36 @@ def tv(x: np.ndarray) -> float:
     return float(np.sqrt((grad(x) ** 2).sum(axis=0)).sum())
 
 
+# Directional TV (Section 3; Ehrhardt & Betcke, SIAM J. Imaging Sci. 9,
+# 2016): K = D grad with D_j = I - xi_j xi_j^T, which removes from the
+# finite-difference vector of voxel j its component along the normalised
+# gradient of a structural prior image v:
+#   xi = grad v / sqrt(|grad v|^2 + eta^2).
+# Readings: the full projection (no weight below one on xi xi^T); eta is an
+# input; ||D grad|| <= ||grad|| (|D_j| <= 1), so the step sizes keep ||grad||.
+
+
+def dtv_field(v: np.ndarray, eta: float) -> np.ndarray:
+    """xi of the DTV prior for the prior image v, [3][nz][ny][nx]."""
+    gv = grad(np.asarray(v, dtype=np.float64))
+    return gv / np.sqrt((gv ** 2).sum(axis=0) + eta * eta)[None]
+
+
+def dtv_project(xi: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """D q = q - xi (xi . q) per voxel (D is symmetric)."""
+    return q - xi * (xi * q).sum(axis=0)[None]
+
+
+def k_op(x: np.ndarray, xi: Optional[np.ndarray] = None) -> np.ndarray:
+    """K x: grad x for TV, D grad x for DTV."""
+    return grad(x) if xi is None else dtv_project(xi, grad(x))
+
+
+def k_adj(w: np.ndarray, xi: Optional[np.ndarray] = None) -> np.ndarray:
+    """K^T w: grad^T w for TV, grad^T D w for DTV."""
+    return grad_adjoint(w if xi is None else dtv_project(xi, w))
+
+
 # --------------------------------------------------------------------------
 # data term
 
@@ -308,11 +339,14 @@ def poisson_dual_conj(y: np.ndarray, d: np.ndarray) -> np.ndarray:
     return out
 
 
-def cost(geom: Geometry, x: np.ndarray, events, s: np.ndarray, g: np.ndarray, beta: float) -> float:
+def cost(geom: Geometry, x: np.ndarray, events, s: np.ndarray, g: np.ndarray, beta: float,
+         xi: Optional[np.ndarray] = None) -> float:
     """Listmode form of Eq. (1) without the constant sum of s over all bins:
-    <g, x> - sum_e log((P^LM x)_e + s_e) + beta ||K x||_{2,1}."""
+    <g, x> - sum_e log((P^LM x)_e + s_e) + beta ||K x||_{2,1} (K of DTV
+    when xi is given)."""
     q = fwd(geom, x, events) + s
-    return float((g * x).sum() - np.log(q).sum() + beta * tv(x))
+    prior = float(np.sqrt((k_op(x, xi) ** 2).sum(axis=0)).sum())
+    return float((g * x).sum() - np.log(q).sum() + beta * prior)
 
 
 # --------------------------------------------------------------------------
@@ -338,10 +372,11 @@ class LMSetup:
     T: np.ndarray
     g: np.ndarray
     knorm: float
+    xi: Optional[np.ndarray] = None  # DTV field; None: TV
 
 
 def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
-             rho: float, knorm: Optional[float] = None) -> LMSetup:
+             rho: float, knorm: Optional[float] = None, xi: Optional[np.ndarray] = None) -> LMSetup:
     """Event counts, subsets and step sizes (Algorithm 2, preprocessing;
     Eq. lm_stepsizes)."""
     ev = _ev(events)
@@ -352,7 +387,7 @@ def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float
     S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
     kn = grad_norm(geom.shape) if (knorm is None or knorm <= 0) else float(knorm)
     T = rho / (2.0 * gamma * np.maximum(g, kn))
-    return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn)
+    return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn, xi=xi)
 
 
 def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarray) -> LMState:
@@ -363,7 +398,7 @@ def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarra
     x = np.array(x0, dtype=np.float64).reshape(geom.shape)
     y = 1.0 - setup.mu / (fwd(geom, x, ev) + s)
     w = np.zeros((3,) + geom.shape)
-    z = setup.g + back(geom, (y - 1.0) / setup.mu, ev) + grad_adjoint(w)
+    z = setup.g + back(geom, (y - 1.0) / setup.mu, ev) + k_adj(w, setup.xi)
     return LMState(x=x, z=z, zbar=z.copy(), w=w, y=y, u=0)
 
 
@@ -382,9 +417,9 @@ def lm_update(geom: Geometry, events, s: np.ndarray, setup: LMSetup, st: LMState
         st.y[e] = yp
         p = 1.0 / (2.0 * n_subsets)
     else:
-        v = st.w + setup.S_prior * grad(st.x)
+        v = st.w + setup.S_prior * k_op(st.x, setup.xi)
         wp = prox_tv_dual(v, beta)
-        dz = grad_adjoint(wp - st.w)
+        dz = k_adj(wp - st.w, setup.xi)
         st.w = wp
         p = 0.5
     st.z = st.z + dz
@@ -397,13 +432,14 @@ def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarra
              n_subsets: int, seq: Sequence[int], gamma: float, rho: float, beta: float,
              knorm: Optional[float] = None, state: Optional[LMState] = None,
              setup: Optional[LMSetup] = None,
-             callback: Optional[Callable[[LMState, LMSetup], None]] = None):
+             callback: Optional[Callable[[LMState, LMSetup], None]] = None,
+             xi: Optional[np.ndarray] = None):
     """Run the updates listed in ``seq`` (each entry a subset index, or
     n_subsets for the prior) and return (x, state, setup).  x is the image of
     the last x-update (the value Algorithm 2 returns)."""
     s = np.asarray(s, dtype=np.float64)
     if setup is None:
-        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm)
+        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm, xi)
     if state is None:
         state = lm_init(geom, events, s, setup, x0)
     for i in seq:
@@ -420,7 +456,8 @@ def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarra
 
 def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins_of_subset,
                seq, gamma: float, rho: float, beta: float, shape_zyx,
-               T: Optional[np.ndarray] = None, knorm: Optional[float] = None):
+               T: Optional[np.ndarray] = None, knorm: Optional[float] = None,
+               xi: Optional[np.ndarray] = None):
     """P: [m, nvox] rows of the TOF sinogram operator; d: counts per bin;
     bins_of_subset: list of bin-index arrays; T: primal step, by default the
     preconditioned rule of Algorithm 1, T = min_k T_k with
@@ -437,7 +474,7 @@ def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins
     x = np.array(x0, dtype=np.float64).reshape(-1)
     y = 1.0 - d / (P @ x + s)
     w = np.zeros((3,) + tuple(shape_zyx))
-    z = P.T @ y + grad_adjoint(w).reshape(-1)
+    z = P.T @ y + k_adj(w, xi).reshape(-1)
     zbar = z.copy()
     Tf = np.asarray(T, dtype=np.float64).reshape(-1)
     for i in seq:
@@ -450,9 +487,9 @@ def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins
             y[b] = yp
             p = 1.0 / (2.0 * n)
         else:
-            v = w + S_prior * grad(x.reshape(shape_zyx))
+            v = w + S_prior * k_op(x.reshape(shape_zyx), xi)
             wp = prox_tv_dual(v, beta)
-            dz = grad_adjoint(wp - w).reshape(-1)
+            dz = k_adj(wp - w, xi).reshape(-1)
             w = wp
             p = 0.5
         z = z + dz
