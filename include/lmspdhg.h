@@ -179,6 +179,19 @@ int lm_spdhg_init(lm_plan *p, const float *x0, void *stream);
  * stream).  LM_EINVAL if an entry of seq is out of range (nothing run). */
 int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq_host, int32_t n_updates, void *stream);
 
+/* Directional TV prior (Section 3, DTV; Ehrhardt & Betcke 2016) in place of
+ * TV: K = D grad with D_j = I - xi_j xi_j^T, which removes from each
+ * voxel's finite-difference vector its component along the normalised
+ * gradient xi = grad v / sqrt(|grad v|^2 + eta^2) of the structural prior
+ * image v (row-major float[nz][ny][nx], device; the paper's experiments use
+ * the image itself with flipped contrast).  The prior updates of later
+ * lm_spdhg_epoch calls use it: w <- proj_beta(w + S_prior K x), z gains
+ * K^T of the change of w.  The step sizes keep ||grad|| (|D_j| <= 1).
+ * v = NULL returns to TV.  The first call allocates two more images of
+ * ncomp components (stream-ordered); work is enqueued on stream.  LM_EINVAL
+ * for eta <= 0. */
+int lm_plan_set_prior_image(lm_plan *p, const float *v, double eta, void *stream);
+
 /* Number of events, subsets and the image size of a plan (host outputs,
  * any may be NULL). */
 int lm_plan_info(const lm_plan *p, int64_t *n_ev, int32_t *n_sub, int64_t *nvox);

@@ -260,6 +260,14 @@ class Plan:
                                      _stream(self.geom.device)), "lm_spdhg_epoch")
         return x
 
+    def set_prior_image(self, v: Optional[torch.Tensor], eta: float = 0.0) -> None:
+        """Directional TV: later prior updates use K = D grad with the
+        normalised gradient of the prior image v (eta > 0); None: TV."""
+        if v is not None:
+            _need(v, torch.float32, "v", self.geom.device, self.geom.nvox)
+        _lib.check(_L.lm_plan_set_prior_image(self._handle(), _ptr(v), float(eta), _stream(self.geom.device)),
+                   "lm_plan_set_prior_image")
+
     def lists(self):
         """(y, mu, subset, P^LM 1) per event in the caller's order."""
         n, dev = self.n_events, self.geom.device

@@ -1,0 +1,21 @@
+// Launchers of the directional TV prior (defined in lm_dtv.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lm_device.hpp"
+
+namespace lmk {
+
+// xi = grad v / sqrt(|grad v|^2 + eta^2) of the row-major prior image v,
+// written in layout L (ncomp components of ne elements; padding untouched).
+int launch_dtv_field(const int n[3], const Layout &L, int ncomp, long long ne, const float *v, float eta, float *xi,
+                     hipStream_t st);
+
+// Prior update of LM-SPDHG with K = D grad, D = I - xi xi^T, up to the
+// z / zbar step: w_out = proj_beta(w + Sp D grad x), then dz = grad^T D
+// (w_out - w) (pd holds D (w_out - w), ncomp components).  All in layout L.
+int launch_dtv_prior(const int n[3], const Layout &L, int ncomp, long long ne, const float *x, const float *w,
+                     float *w_out, const float *xi, float *pd, float *dz, float Sp, float beta, hipStream_t st);
+
+}  // namespace lmk

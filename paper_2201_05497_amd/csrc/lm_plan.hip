@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "lm_device.hpp"
+#include "lm_dtv.hpp"
 #include "lm_host.hpp"
 #include "lm_image.hpp"
 
@@ -70,6 +71,10 @@ struct lm_plan {
   // images, brick layout
   float *gimg = nullptr, *T = nullptr, *z = nullptr, *zbar = nullptr, *dz = nullptr;
   float *w = nullptr, *wn = nullptr, *xint = nullptr, *xalt = nullptr;
+  // directional TV (lm_plan_set_prior_image): xi and D (w_new - w), ncomp
+  // components each; dtv selects that prior over TV
+  float *xi_dtv = nullptr, *pd = nullptr;
+  bool dtv = false;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
@@ -500,6 +505,16 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
             return lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
           }))
         return rc;
+    } else if (p->dtv) {
+      // K = D grad: dual step and adjoint, then z / zbar (and the fused
+      // primal step, in place) as after a data update
+      if (int rc = timed(p, LM_K_TV, st, [&] {
+            int r = lmk::launch_dtv_prior(p->G.n, p->lay, p->ncomp, E, xi, p->w, p->wn, p->xi_dtv, p->pd, p->dz,
+                                          (float)p->Sp, (float)p->beta, st);
+            return r ? r : lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_prior, fuse, E, st);
+          }))
+        return rc;
+      std::swap(p->w, p->wn);
     } else {
       if (int rc = timed(p, LM_K_TV, st, [&] {
             return lmk::launch_tv_fused(p->G.n, p->lay, p->ncomp, xi, p->w, p->wn, p->z, p->xalt, p->T, p->zbar,
@@ -514,6 +529,25 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
   }
   if (int rc = timed(p, LM_K_PRIMAL, st, [&] { return lmk::launch_from_layout(p->G.n, p->lay, 1, xi, x, st); }))
     return rc;
+  return LM_OK;
+}
+
+int lm_plan_set_prior_image(lm_plan *p, const float *v, double eta, void *stream) {
+  lmh::clear_error();
+  LM_REQUIRE(p, LM_EINVAL, "NULL plan");
+  if (!v) {
+    p->dtv = false;
+    return LM_OK;
+  }
+  LM_REQUIRE(eta > 0.0 && std::isfinite(eta), LM_EINVAL, "eta must be positive and finite");
+  hipStream_t st = lmh::as_stream(stream);
+  p->last = st;
+  if (!p->xi_dtv) {
+    if (int rc = dalloc(p, &p->xi_dtv, (size_t)(p->ne * p->ncomp))) return rc;
+    if (int rc = dalloc(p, &p->pd, (size_t)(p->ne * p->ncomp))) return rc;
+  }
+  if (int rc = lmk::launch_dtv_field(p->G.n, p->lay, p->ncomp, p->ne, v, (float)eta, p->xi_dtv, st)) return rc;
+  p->dtv = true;
   return LM_OK;
 }
 

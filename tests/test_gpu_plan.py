@@ -59,12 +59,13 @@ def _gamma(x0):
     return float(np.float32(3.0 / float(x0.max())))
 
 
-def _plan(P, p, n_sub, g, beta, events=None, s=None):
+def _plan(P, p, n_sub, g, beta, events=None, s=None, gamma=None, rho=RHO):
     Gg = P.Geometry.from_problem(p)
     ev = p.events if events is None else events
     ss = p.s if s is None else s
     plan = P.Plan(Gg, Gg.events(ev), torch.as_tensor(np.asarray(ss, np.float32), device="cuda"), n_sub,
-                  _gamma(p.x0), RHO, beta, g=None if g is None else torch.as_tensor(g.astype(np.float32), device="cuda"))
+                  _gamma(p.x0) if gamma is None else gamma, rho, beta,
+                  g=None if g is None else torch.as_tensor(g.astype(np.float32), device="cuda"))
     return Gg, plan
 
 
@@ -94,7 +95,8 @@ def test_preprocessing_2d(P):
     assert emax <= PROJ_TOL and eg <= ITER_TOL and eT <= ITER_TOL
 
 
-def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=None, s=None):
+def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=None, s=None, gamma=None,
+                 rho=RHO, xi=None):
     Go = oracle.Geometry.from_problem(p)
     ev = p.events if events is None else events
     ss = (p.s if s is None else s).astype(np.float64)
@@ -106,8 +108,9 @@ def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=
     for ep in range(epochs):
         seq = lmsynth.subset_sequence(seed, ep * 2 * n_sub, 2 * n_sub, n_sub)
         plan.epoch(x, seq)
-        x_o, st, su = oracle.lm_spdhg(Go, ev, ss, g_orc, p.x0, n_sub, seq, _gamma(p.x0), RHO, beta,
-                                      state=st, setup=su)
+        x_o, st, su = oracle.lm_spdhg(Go, ev, ss, g_orc, p.x0, n_sub, seq,
+                                      _gamma(p.x0) if gamma is None else gamma, rho, beta, state=st, setup=su,
+                                      xi=xi)
         e = img_err(x.cpu().numpy(), x_o)
         errs.append(e)
         report(f"{name} epoch {ep + 1}", x_err=e)
@@ -134,6 +137,34 @@ def test_lm_spdhg_2d_10_epochs(P):
     p = problem_2d()
     Gg, plan = _plan(P, p, 28, None, 0.03)
     _run_compare(P, p, Gg, plan, sens_2d(), 28, 0.03, 10, 2000, "2d")
+
+
+def test_accelerated_parameters_2d(P):
+    """The accelerated choice of the supplement, rho = 8 and gamma =
+    30 / max(x0): the same step-size rules with rho > 1 (no convergence
+    guarantee), 5 epochs of the 2D workload against the oracle."""
+    p = problem_2d()
+    gamma = float(np.float32(30.0 / float(p.x0.max())))
+    Gg, plan = _plan(P, p, 28, None, 0.03, gamma=gamma, rho=8.0)
+    _run_compare(P, p, Gg, plan, sens_2d(), 28, 0.03, 5, 2004, "2d rho=8", gamma=gamma, rho=8.0)
+
+
+def test_dtv_prior_2d(P):
+    """LM-SPDHG with the DTV prior (Section 3) on the 2D workload, the
+    paper's perfect structural information: the prior image is the phantom
+    with flipped contrast (eta = 1 % of its largest gradient); 5 epochs
+    against the oracle.  A None image returns the plan to TV; eta = 0 is
+    rejected."""
+    p = problem_2d()
+    v = (p.x_true.max() - p.x_true).astype(np.float32)
+    eta = 0.01 * float(np.sqrt((oracle.grad(v.astype(np.float64)) ** 2).sum(0)).max())
+    Gg, plan = _plan(P, p, 28, None, 0.03)
+    plan.set_prior_image(torch.as_tensor(v, device="cuda"), eta)
+    xi = oracle.dtv_field(v.astype(np.float64), eta)
+    _run_compare(P, p, Gg, plan, sens_2d(), 28, 0.03, 5, 2005, "2d dtv", xi=xi)
+    plan.set_prior_image(None)
+    with pytest.raises(P.LMError):
+        plan.set_prior_image(torch.as_tensor(v, device="cuda"), 0.0)
 
 
 def test_lm_spdhg_3d_reduced(P):
@@ -405,13 +436,15 @@ def test_prior_updates_ragged_grids(P, shape):
     assert ex <= ITER_TOL and ez <= ITER_TOL and ew <= ITER_TOL
 
 
-@pytest.mark.parametrize("shape", [(37, 29, 11), (20, 33, 18)])
-def test_mixed_updates_ragged_grids(P, shape):
+@pytest.mark.parametrize("shape,dtv", [((37, 29, 11), False), ((20, 33, 18), False), ((37, 29, 11), True),
+                                       ((20, 33, 18), True)])
+def test_mixed_updates_ragged_grids(P, shape, dtv):
     """Mixed data and prior updates from a random state on ragged 3D grids,
     over two calls, against the oracle: data updates followed by prior
     updates and by data updates, prior updates in a row, and calls that end
     with either kind (the last update of a call materialises zbar instead
-    of fusing the next primal step)."""
+    of fusing the next primal step); with the TV prior and with the DTV
+    prior of a smooth structural image."""
     nx, ny, nz = shape
     sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
     tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
@@ -429,12 +462,16 @@ def test_mixed_updates_ragged_grids(P, shape):
     w0 *= np.minimum(1.0, beta / np.maximum(np.sqrt((w0.astype(np.float64) ** 2).sum(0)), 1e-30)).astype(np.float32)
     c0 = rng.uniform(0.2, 0.8, len(p.events)).astype(np.float32)
     Go = oracle.Geometry.from_problem(p)
-    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO)
+    v, eta = smooth_image(zyx, 79, base=2.0), 0.05
+    xi = oracle.dtv_field(v.astype(np.float64), eta) if dtv else None
+    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO, xi=xi)
     st = oracle.LMState(x=x_start.astype(np.float64), z=z0.astype(np.float64), zbar=zb0.astype(np.float64),
                         w=w0.astype(np.float64), y=1.0 - c0.astype(np.float64), u=0)
     calls = [np.array([0, 4, 4, 1, 4, 2, 3, 4, 0, 4], np.int32), np.array([4, 1, 4, 2, 2, 4, 3, 4], np.int32)]
     Gg, plan = _plan(P, p, n, g, beta)
     cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+    if dtv:
+        plan.set_prior_image(cuda(v), eta)
     plan.set_state({"z": cuda(z0), "zbar": cuda(zb0), "w": cuda(w0), "c": cuda(c0), "u": 0})
     x = cuda(x_start)
     for k, seq in enumerate(calls):
@@ -448,5 +485,5 @@ def test_mixed_updates_ragged_grids(P, shape):
         ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
         wg = state["w"].cpu().numpy().astype(np.float64)
         ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
-        report(f"mixed updates {shape} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
+        report(f"mixed updates {shape} dtv={dtv} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
         assert max(ex, ez, ezb, ec, ew) <= ITER_TOL
