@@ -17,7 +17,8 @@ second over the timed epochs, the roofline of the dominant kernel (the
 fused data update, on its algorithmic bytes) and its binding resource (its
 FP32 atomic requests per second against a ceiling calibrated in the same
 run), the FP64 oracle timed on a bounded sample of the same workload on the
-host (cpu_baseline), the warm start of the same workload (one listmode
+host (cpu_baseline), the same reconstruction continued with the DTV prior
+(ms per epoch and per prior update), the warm start of the same workload (one listmode
 EM-TV iteration, 28 subsets, 20 accelerated PDHG steps per denoising, with
 the time and bandwidth of one denoising step), seconds per epoch of the 2D
 workload (1e5 events,
@@ -78,6 +79,10 @@ BYTES_PER_EVENT_PROJ = 10 + 4
 # reads ubar and q (4 + 12) and writes q (12); the primal pass reads u, z,
 # w and q (4 + 4 + 4 + 12) and writes u and ubar (8).
 BYTES_PER_VOXEL_PD = 28 + 32
+# A DTV prior update, per voxel: the dual pass reads x, w and xi (4 + 12 +
+# 12) and writes w and D (w_new - w) (12 + 12); the adjoint pass reads the
+# latter (12) and writes dz (4); the z / zbar / primal pass moves 28.
+BYTES_PER_VOXEL_DTV = 52 + 16 + 28
 WARM_SUBSETS = 28               # the paper's warm start: 1 EM-TV iteration, 28 subsets,
 WARM_DENOISE = 20               # 20 accelerated PDHG steps per denoising
 
@@ -337,6 +342,7 @@ def epoch_leg(args, torch, P, lmsynth):
     t_total = time.perf_counter() - t0
     timing = plan.get_timing() if args.timing_every > 0 else None
     plan.timing(0)
+    dtv = dtv_epochs(torch, P, lmsynth, plan, x, G, u)
     plan.destroy()
 
     timed = seqs[args.warmup:]
@@ -394,9 +400,41 @@ def epoch_leg(args, torch, P, lmsynth):
         "roofline": roof,
         "binding": bind,
         "kernels": kernels,
+        "dtv": dtv,
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create": round(t_plan, 3)},
     }
     return out, p, G, g
+
+
+def dtv_epochs(torch, P, lmsynth, plan, x, G, u0, epochs: int = 2):
+    """The same reconstruction continued with the DTV prior (Section 3) for
+    one warm-up and `epochs` timed epochs; the structural prior image is
+    the phantom with flipped contrast (eta = 1 % of its largest gradient).
+    One further epoch brackets every prior update with HIP events."""
+    v = lmsynth.phantom_3d_ellipsoid(lmsynth.config_3d().image).astype(np.float32)
+    v = v.max() - v
+    gm = np.sqrt(sum(np.diff(v.astype(np.float64), axis=a, append=v[(slice(None),) * a + (slice(-1, None),)]) ** 2
+                     for a in range(3)))
+    plan.set_prior_image(torch.as_tensor(v, device=G.device), 0.01 * float(gm.max()))
+    seqs = [lmsynth.subset_sequence(SEQ_SEED, u0 + k * 2 * N_SUB, 2 * N_SUB, N_SUB) for k in range(2 + epochs)]
+    plan.epoch(x, seqs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for seq in seqs[1:-1]:
+        plan.epoch(x, seq)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # one more epoch with every launch bracketed, for the prior update alone
+    plan.timing(1)
+    plan.epoch(x, seqs[-1])
+    ms, cnt = plan.get_timing()["tv"]
+    plan.timing(0)
+    plan.set_prior_image(None)
+    us = 1e3 * ms / max(cnt, 1)
+    log(f"DTV: {1e3 * t / epochs:.2f} ms/epoch, {us:.1f} us per prior update")
+    return {"ms_per_epoch": round(1e3 * t / epochs, 3), "prior_update_us": round(us, 2),
+            "prior_updates_timed": cnt,
+            "prior_update_GBs": round(BYTES_PER_VOXEL_DTV * G.nvox / (us * 1e-6) / 1e9, 1)}
 
 
 # --------------------------------------------------------------------------- warm start
