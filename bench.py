@@ -80,9 +80,10 @@ BYTES_PER_EVENT_PROJ = 10 + 4
 # w and q (4 + 4 + 4 + 12) and writes u and ubar (8).
 BYTES_PER_VOXEL_PD = 28 + 32
 # A DTV prior update, per voxel: the dual pass reads x, w and xi (4 + 12 +
-# 12) and writes w and D (w_new - w) (12 + 12); the adjoint pass reads the
-# latter (12) and writes dz (4); the z / zbar / primal pass moves 28.
-BYTES_PER_VOXEL_DTV = 52 + 16 + 28
+# 12) and writes w and D (w_new - w) (12 + 12); the adjoint pass, fused with
+# z / zbar and the primal step, reads the latter, z, T and x (12 + 12) and
+# writes z and x (8).
+BYTES_PER_VOXEL_DTV = 52 + 32
 WARM_SUBSETS = 28               # the paper's warm start: 1 EM-TV iteration, 28 subsets,
 WARM_DENOISE = 20               # 20 accelerated PDHG steps per denoising
 

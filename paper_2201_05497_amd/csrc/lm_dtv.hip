@@ -7,10 +7,11 @@
 //
 // The prior update is two passes over the plan's bricked images: the dual
 // step (forward differences of x at the voxel, D, the projection onto the
-// beta-ball) storing D (w_out - w), and its adjoint stencil into dz; the z /
-// zbar / primal step then runs as after a data update.  Each voxel reads x,
-// w, xi and writes w_out and D (w_out - w) (ncomp components each), then
-// the adjoint reads them back: bound by HBM bandwidth.
+// beta-ball) storing D (w_out - w), then its adjoint stencil fused with the
+// z / zbar step and the next primal step.  The first pass reads x, w, xi and
+// writes w_out and D (w_out - w) (ncomp components each); the second reads
+// the latter back with z, T and x and writes z and x (or zbar): bound by
+// HBM bandwidth.
 #include <hip/hip_runtime.h>
 
 #include "lm_dtv.hpp"
@@ -80,19 +81,21 @@ __global__ __launch_bounds__(kBlock) void k_dtv_dual(const float *__restrict__ x
   }
 }
 
-// dz = grad^T pd: sum over axes of pd_a at the lower neighbour (if any)
-// minus pd_a at the voxel (unless it is in the last layer).  Padding gets 0.
-__global__ __launch_bounds__(kBlock) void k_dtv_adjoint(const float *__restrict__ pd, float *__restrict__ dz,
-                                                        lmk::Layout L, int nx, int ny, int nz, long long ne,
-                                                        int ncomp) {
+// dz = grad^T pd (the sum over axes of pd_a at the lower neighbour, if
+// any, minus pd_a at the voxel, unless it is in the last layer), then
+//   z += dz;  zbar = z + dz / p;  (fuse ? x = max(0, x - T zbar) : store zbar).
+// x is read and written at the thread's own voxel only.  Padding positions
+// are left alone (they stay zero).
+__global__ __launch_bounds__(kBlock) void k_dtv_adjoint_image(const float *__restrict__ pd, float *__restrict__ z,
+                                                              float *__restrict__ x, const float *__restrict__ T,
+                                                              float *__restrict__ zbar, float inv_p, int fuse,
+                                                              lmk::Layout L, int nx, int ny, int nz, long long ne,
+                                                              int ncomp) {
   const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int i, j, k;
   lmk::vpos(L, p, i, j, k);
-  if (i >= nx || j >= ny || k >= nz) {
-    dz[p] = 0.0f;
-    return;
-  }
+  if (i >= nx || j >= ny || k >= nz) return;
   float s = 0.0f;
   if (i > 0) s += pd[lmk::vidx(L, i - 1, j, k)];
   if (i + 1 < nx) s -= pd[p];
@@ -102,7 +105,13 @@ __global__ __launch_bounds__(kBlock) void k_dtv_adjoint(const float *__restrict_
     if (k > 0) s += pd[2 * ne + lmk::vidx(L, i, j, k - 1)];
     if (k + 1 < nz) s -= pd[2 * ne + p];
   }
-  dz[p] = s;
+  const float zn = z[p] + s;
+  const float zb = fmaf(s, inv_p, zn);
+  z[p] = zn;
+  if (fuse)
+    x[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
+  else
+    zbar[p] = zb;
 }
 
 }  // namespace
@@ -118,12 +127,14 @@ int launch_dtv_field(const int n[3], const Layout &L, int ncomp, long long ne, c
   return LM_OK;
 }
 
-int launch_dtv_prior(const int n[3], const Layout &L, int ncomp, long long ne, const float *x, const float *w,
-                     float *w_out, const float *xi, float *pd, float *dz, float Sp, float beta, hipStream_t st) {
+int launch_dtv_prior(const int n[3], const Layout &L, int ncomp, long long ne, float *x, const float *w,
+                     float *w_out, const float *xi, float *pd, float *z, const float *T, float *zbar, float Sp,
+                     float beta, float inv_p, bool fuse, hipStream_t st) {
   hipLaunchKernelGGL(k_dtv_dual, dim3(grid_for(ne)), dim3(kBlock), 0, st, x, w, w_out, xi, pd, L, n[0], n[1], n[2],
                      ne, ncomp, Sp, beta);
   LM_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_dtv_adjoint, dim3(grid_for(ne)), dim3(kBlock), 0, st, pd, dz, L, n[0], n[1], n[2], ne, ncomp);
+  hipLaunchKernelGGL(k_dtv_adjoint_image, dim3(grid_for(ne)), dim3(kBlock), 0, st, pd, z, x, T, zbar, inv_p,
+                     fuse ? 1 : 0, L, n[0], n[1], n[2], ne, ncomp);
   LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }

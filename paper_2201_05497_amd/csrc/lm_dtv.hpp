@@ -12,10 +12,12 @@ namespace lmk {
 int launch_dtv_field(const int n[3], const Layout &L, int ncomp, long long ne, const float *v, float eta, float *xi,
                      hipStream_t st);
 
-// Prior update of LM-SPDHG with K = D grad, D = I - xi xi^T, up to the
-// z / zbar step: w_out = proj_beta(w + Sp D grad x), then dz = grad^T D
-// (w_out - w) (pd holds D (w_out - w), ncomp components).  All in layout L.
-int launch_dtv_prior(const int n[3], const Layout &L, int ncomp, long long ne, const float *x, const float *w,
-                     float *w_out, const float *xi, float *pd, float *dz, float Sp, float beta, hipStream_t st);
+// Prior update of LM-SPDHG with K = D grad, D = I - xi xi^T:
+// w_out = proj_beta(w + Sp D grad x), dz = grad^T D (w_out - w) (pd holds
+// D (w_out - w), ncomp components), z += dz, zbar = z + dz inv_p, and
+// fuse ? x = max(0, x - T zbar) in place : store zbar.  All in layout L.
+int launch_dtv_prior(const int n[3], const Layout &L, int ncomp, long long ne, float *x, const float *w,
+                     float *w_out, const float *xi, float *pd, float *z, const float *T, float *zbar, float Sp,
+                     float beta, float inv_p, bool fuse, hipStream_t st);
 
 }  // namespace lmk

@@ -506,12 +506,11 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
           }))
         return rc;
     } else if (p->dtv) {
-      // K = D grad: dual step and adjoint, then z / zbar (and the fused
-      // primal step, in place) as after a data update
+      // K = D grad: the dual step, then the adjoint fused with z / zbar and
+      // the next primal step (in place)
       if (int rc = timed(p, LM_K_TV, st, [&] {
-            int r = lmk::launch_dtv_prior(p->G.n, p->lay, p->ncomp, E, xi, p->w, p->wn, p->xi_dtv, p->pd, p->dz,
-                                          (float)p->Sp, (float)p->beta, st);
-            return r ? r : lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_prior, fuse, E, st);
+            return lmk::launch_dtv_prior(p->G.n, p->lay, p->ncomp, E, xi, p->w, p->wn, p->xi_dtv, p->pd, p->z,
+                                         p->T, p->zbar, (float)p->Sp, (float)p->beta, inv_p_prior, fuse, st);
           }))
         return rc;
       std::swap(p->w, p->wn);
