@@ -373,21 +373,28 @@ class LMSetup:
     g: np.ndarray
     knorm: float
     xi: Optional[np.ndarray] = None  # DTV field; None: TV
+    m: Optional[np.ndarray] = None   # per-event multiplicative factors; None: 1
 
 
 def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
-             rho: float, knorm: Optional[float] = None, xi: Optional[np.ndarray] = None) -> LMSetup:
+             rho: float, knorm: Optional[float] = None, xi: Optional[np.ndarray] = None,
+             m: Optional[np.ndarray] = None) -> LMSetup:
     """Event counts, subsets and step sizes (Algorithm 2, preprocessing;
-    Eq. lm_stepsizes)."""
+    Eq. lm_stepsizes).  m: per-event multiplicative factors of the forward
+    model (attenuation times normalisation of the event's LOR), so that the
+    operator is P' = diag(m) P^LM; g must then be the sensitivity of P'."""
     ev = _ev(events)
     mu = event_counts(ev, geom.n_cry)
     sub = subset_ids(len(ev), n_subsets)
     subsets = [np.nonzero(sub == i)[0] for i in range(n_subsets)]
     P1 = fwd(geom, np.ones(geom.shape), ev)
+    if m is not None:
+        P1 = np.asarray(m, dtype=np.float64) * P1
     S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
     kn = grad_norm(geom.shape) if (knorm is None or knorm <= 0) else float(knorm)
     T = rho / (2.0 * gamma * np.maximum(g, kn))
-    return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn, xi=xi)
+    return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn, xi=xi,
+                   m=None if m is None else np.asarray(m, dtype=np.float64))
 
 
 def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarray) -> LMState:
@@ -396,9 +403,10 @@ def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarra
     in the module doc)."""
     ev = _ev(events)
     x = np.array(x0, dtype=np.float64).reshape(geom.shape)
-    y = 1.0 - setup.mu / (fwd(geom, x, ev) + s)
+    m = np.ones(len(ev)) if setup.m is None else setup.m
+    y = 1.0 - setup.mu / (m * fwd(geom, x, ev) + s)
     w = np.zeros((3,) + geom.shape)
-    z = setup.g + back(geom, (y - 1.0) / setup.mu, ev) + k_adj(w, setup.xi)
+    z = setup.g + back(geom, m * (y - 1.0) / setup.mu, ev) + k_adj(w, setup.xi)
     return LMState(x=x, z=z, zbar=z.copy(), w=w, y=y, u=0)
 
 
@@ -410,10 +418,11 @@ def lm_update(geom: Geometry, events, s: np.ndarray, setup: LMSetup, st: LMState
     st.x = np.maximum(0.0, st.x - setup.T * st.zbar)
     if i < n_subsets:
         e = setup.subsets[i]
-        q = fwd(geom, st.x, ev[e]) + s[e]
+        me = 1.0 if setup.m is None else setup.m[e]
+        q = me * fwd(geom, st.x, ev[e]) + s[e]
         a = st.y[e] + setup.S[e] * q
         yp = prox_poisson_dual(a, setup.S[e], setup.mu[e])
-        dz = back(geom, (yp - st.y[e]) / setup.mu[e], ev[e])
+        dz = back(geom, me * (yp - st.y[e]) / setup.mu[e], ev[e])
         st.y[e] = yp
         p = 1.0 / (2.0 * n_subsets)
     else:
@@ -433,13 +442,13 @@ def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarra
              knorm: Optional[float] = None, state: Optional[LMState] = None,
              setup: Optional[LMSetup] = None,
              callback: Optional[Callable[[LMState, LMSetup], None]] = None,
-             xi: Optional[np.ndarray] = None):
+             xi: Optional[np.ndarray] = None, m: Optional[np.ndarray] = None):
     """Run the updates listed in ``seq`` (each entry a subset index, or
     n_subsets for the prior) and return (x, state, setup).  x is the image of
     the last x-update (the value Algorithm 2 returns)."""
     s = np.asarray(s, dtype=np.float64)
     if setup is None:
-        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm, xi)
+        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm, xi, m)
     if state is None:
         state = lm_init(geom, events, s, setup, x0)
     for i in seq:
