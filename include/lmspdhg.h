@@ -51,7 +51,7 @@ extern "C" {
 enum {
   LM_OK = 0,
   LM_EINVAL = -1, /* bad shape, size or parameter */
-  LM_ERANGE = -2, /* crystal, ring or TOF index out of range */
+  LM_ERANGE = -2, /* crystal, ring or TOF index out of range; an event factor <= 0 */
   LM_ENOMEM = -3, /* device allocation failed */
   LM_EHIP = -4,   /* a HIP runtime call failed (message has the HIP text) */
   LM_ESTATE = -5  /* plan used before lm_spdhg_init, or inconsistent state */
@@ -178,6 +178,23 @@ int lm_spdhg_init(lm_plan *p, const float *x0, void *stream);
  * value Algorithm 2 returns).  Calls on one plan must be ordered (one
  * stream).  LM_EINVAL if an entry of seq is out of range (nothing run). */
 int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq_host, int32_t n_updates, void *stream);
+
+/* Per-event multiplicative factors of the forward model (Section 1: P
+ * includes attenuation and normalisation; m_e is that factor for the LOR of
+ * event e), so that the plan's operator becomes P' = diag(m) P^LM.  The g
+ * given to lm_plan_create must then be the sensitivity of P' (the sum over
+ * all LORs of m P^T 1).  The factors fold into the stored lists exactly.
+ * With S' = gamma rho / (m P^LM 1):
+ *   S' (m P x + s) = S (P x + s/m),
+ *   the prox term 4 S' mu = 4 S (mu/m),
+ *   P'^T (dy / mu) = P^T (dy / (mu/m)).
+ * So the plan stores s/m and mu/m, and keeps m (4 B per event) so that
+ * lm_plan_get_lists still returns the integer counts.  P^LM 1 as read back
+ * stays the geometric one.  m: float[n], device, caller event order.
+ * Synchronous.  Call once, after lm_plan_create and before lm_spdhg_init or
+ * lm_plan_set_state (LM_ESTATE otherwise).  LM_ERANGE if a factor is not
+ * positive and finite (nothing changed). */
+int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream);
 
 /* Directional TV prior (Section 3, DTV; Ehrhardt & Betcke 2016) in place of
  * TV: K = D grad with D_j = I - xi_j xi_j^T, which removes from each

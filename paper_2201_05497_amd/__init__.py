@@ -260,6 +260,14 @@ class Plan:
                                      _stream(self.geom.device)), "lm_spdhg_epoch")
         return x
 
+    def set_event_factors(self, m: torch.Tensor) -> None:
+        """Per-event multiplicative factors (attenuation x normalisation of
+        each event's LOR): the operator becomes diag(m) P.  Once, before
+        init; g must be the sensitivity of that operator."""
+        _need(m, torch.float32, "m", self.geom.device, self.n_events)
+        _lib.check(_L.lm_plan_set_event_factors(self._handle(), m.data_ptr(), _stream(self.geom.device)),
+                   "lm_plan_set_event_factors")
+
     def set_prior_image(self, v: Optional[torch.Tensor], eta: float = 0.0) -> None:
         """Directional TV: later prior updates use K = D grad with the
         normalised gradient of the prior image v (eta > 0); None: TV."""

@@ -75,6 +75,9 @@ struct lm_plan {
   // components each; dtv selects that prior over TV
   float *xi_dtv = nullptr, *pd = nullptr;
   bool dtv = false;
+  // per-event multiplicative factors (lm_plan_set_event_factors), sorted
+  // order; folded into s and mu, kept to return the event counts
+  float *mfac = nullptr;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
@@ -195,6 +198,30 @@ __global__ void k_scatter_f(const float *in, const int *perm, float *out, long l
 __global__ void k_scatter_mu(const float *in, const int *perm, int *out, long long n) {
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) out[perm[j]] = (int)in[j];
+}
+// the same for a plan with factors: the stored mu / m times m, rounded
+__global__ void k_scatter_mu_fac(const float *in, const float *m, const int *perm, int *out, long long n) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[perm[j]] = (int)rintf(in[j] * m[j]);
+}
+
+// Counts factors that are not positive and finite.
+__global__ void k_check_factors(const float *m, long long n, unsigned long long *bad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && !(m[e] > 0.0f && m[e] < INFINITY)) atomicAdd(bad, 1ULL);
+}
+
+// Folds the factor of each event into the stored lists: s -> s / m and
+// mu -> mu / m (sorted position j holds caller event perm[j]).
+__global__ void k_apply_factors(const float *m, const int *perm, int4 *rec, float *mu, float *mfac, long long n) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const float f = m[perm[j]];
+  int4 r = rec[j];
+  r.w = __float_as_int(__int_as_float(r.w) / f);
+  rec[j] = r;
+  mu[j] = mu[j] / f;
+  mfac[j] = f;
 }
 // out[j] = in[perm[j]] (caller -> sorted order)
 __global__ void k_gather_f(const float *in, const int *perm, float *out, long long n) {
@@ -531,6 +558,34 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
   return LM_OK;
 }
 
+int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream) {
+  lmh::clear_error();
+  LM_REQUIRE(p && m, LM_EINVAL, "NULL plan or factors");
+  LM_REQUIRE(!p->initialized, LM_ESTATE, "event factors must be set before lm_spdhg_init");
+  LM_REQUIRE(!p->mfac, LM_ESTATE, "event factors are already set");
+  const long long N = p->n;
+  if (N == 0) return LM_OK;
+  hipStream_t st = lmh::as_stream(stream);
+  p->last = st;
+  unsigned long long *d = nullptr, h = 0;
+  LM_TRY_HIP(hipMallocAsync((void **)&d, sizeof(*d), st));
+  hipError_t e = hipMemsetAsync(d, 0, sizeof(*d), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_check_factors, dim3(grid_for(N)), dim3(kBlock), 0, st, m, N, d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFreeAsync(d, st);
+  LM_TRY_HIP(e);
+  LM_REQUIRE(h == 0, LM_ERANGE, "%llu event factors are not positive and finite", h);
+  if (int rc = dalloc(p, &p->mfac, (size_t)N)) return rc;
+  hipLaunchKernelGGL(k_apply_factors, dim3(grid_for(N)), dim3(kBlock), 0, st, m, p->perm, p->rec, p->mu, p->mfac, N);
+  LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipStreamSynchronize(st));
+  return LM_OK;
+}
+
 int lm_plan_set_prior_image(lm_plan *p, const float *v, double eta, void *stream) {
   lmh::clear_error();
   LM_REQUIRE(p, LM_EINVAL, "NULL plan");
@@ -570,7 +625,10 @@ int lm_plan_get_lists(const lm_plan *p, float *y, int32_t *mu, int32_t *subset, 
     LM_TRY_HIP(hipGetLastError());
   }
   if (mu) {
-    hipLaunchKernelGGL(k_scatter_mu, dim3(grid_for(N)), dim3(kBlock), 0, st, p->mu, p->perm, mu, N);
+    if (p->mfac)
+      hipLaunchKernelGGL(k_scatter_mu_fac, dim3(grid_for(N)), dim3(kBlock), 0, st, p->mu, p->mfac, p->perm, mu, N);
+    else
+      hipLaunchKernelGGL(k_scatter_mu, dim3(grid_for(N)), dim3(kBlock), 0, st, p->mu, p->perm, mu, N);
     LM_TRY_HIP(hipGetLastError());
   }
   if (subset) {
