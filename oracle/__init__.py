@@ -309,6 +309,41 @@ def dtv_project(xi: np.ndarray, q: np.ndarray) -> np.ndarray:
     return q - xi * (xi * q).sum(axis=0)[None]
 
 
+# Image-space resolution model (Section 1: P includes limited spatial
+# resolution): P = G B with B a separable Gaussian convolution.  Readings:
+# FWHM given in voxels per axis, taps truncated at ceil(3 sigma) and
+# normalised to sum 1, zero outside the image (so B is symmetric: B^T = B).
+
+
+def blur(x: np.ndarray, fwhm_vox: Sequence[float]) -> np.ndarray:
+    """B x for an image [nz][ny][nx]; fwhm_vox = (fx, fy, fz) in voxels, 0
+    leaves that axis alone."""
+    out = np.array(x, dtype=np.float64)
+    for comp, ax in enumerate((2, 1, 0)):
+        fw = float(fwhm_vox[comp])
+        if fw <= 0:
+            continue
+        sig = fw / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+        r = int(np.ceil(3.0 * sig))
+        t = np.arange(-r, r + 1)
+        w = np.exp(-t * t / (2.0 * sig * sig))
+        w /= w.sum()
+        n = out.shape[ax]
+        res = np.zeros_like(out)
+        for tk, wk in zip(t, w):
+            # res[j] += wk * out[j + tk] where 0 <= j + tk < n
+            lo, hi = max(0, -tk), min(n, n - tk)
+            if lo >= hi:
+                continue
+            dst = [slice(None)] * 3
+            src = [slice(None)] * 3
+            dst[ax] = slice(lo, hi)
+            src[ax] = slice(lo + tk, hi + tk)
+            res[tuple(dst)] += wk * out[tuple(src)]
+        out = res
+    return out
+
+
 def k_op(x: np.ndarray, xi: Optional[np.ndarray] = None) -> np.ndarray:
     """K x: grad x for TV, D grad x for DTV."""
     return grad(x) if xi is None else dtv_project(xi, grad(x))
@@ -374,27 +409,42 @@ class LMSetup:
     knorm: float
     xi: Optional[np.ndarray] = None  # DTV field; None: TV
     m: Optional[np.ndarray] = None   # per-event multiplicative factors; None: 1
+    fwhm: Optional[Sequence[float]] = None  # resolution model B (voxels); None: none
+
+
+def _fwd_model(geom: Geometry, setup: "LMSetup", x: np.ndarray, ev: np.ndarray, m) -> np.ndarray:
+    """(P' x)_e = m_e (G B x)_e for the events ev (m a scalar or per event)."""
+    xb = x if setup.fwhm is None else blur(x, setup.fwhm)
+    return m * fwd(geom, xb, ev)
+
+
+def _back_model(geom: Geometry, setup: "LMSetup", v: np.ndarray, ev: np.ndarray, m) -> np.ndarray:
+    """P'^T v = B G^T (m v)."""
+    b = back(geom, m * v, ev)
+    return b if setup.fwhm is None else blur(b, setup.fwhm)
 
 
 def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
              rho: float, knorm: Optional[float] = None, xi: Optional[np.ndarray] = None,
-             m: Optional[np.ndarray] = None) -> LMSetup:
+             m: Optional[np.ndarray] = None, fwhm: Optional[Sequence[float]] = None) -> LMSetup:
     """Event counts, subsets and step sizes (Algorithm 2, preprocessing;
     Eq. lm_stepsizes).  m: per-event multiplicative factors of the forward
     model (attenuation times normalisation of the event's LOR), so that the
-    operator is P' = diag(m) P^LM; g must then be the sensitivity of P'."""
+    operator is P' = diag(m) P^LM; fwhm: the resolution model B, P^LM = G B
+    with G the projector; g must be the sensitivity of the whole operator."""
     ev = _ev(events)
     mu = event_counts(ev, geom.n_cry)
     sub = subset_ids(len(ev), n_subsets)
     subsets = [np.nonzero(sub == i)[0] for i in range(n_subsets)]
-    P1 = fwd(geom, np.ones(geom.shape), ev)
+    P1 = fwd(geom, np.ones(geom.shape) if fwhm is None else blur(np.ones(geom.shape), fwhm), ev)
     if m is not None:
         P1 = np.asarray(m, dtype=np.float64) * P1
     S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
     kn = grad_norm(geom.shape) if (knorm is None or knorm <= 0) else float(knorm)
     T = rho / (2.0 * gamma * np.maximum(g, kn))
     return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn, xi=xi,
-                   m=None if m is None else np.asarray(m, dtype=np.float64))
+                   m=None if m is None else np.asarray(m, dtype=np.float64),
+                   fwhm=None if fwhm is None else tuple(float(f) for f in fwhm))
 
 
 def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarray) -> LMState:
@@ -404,9 +454,9 @@ def lm_init(geom: Geometry, events, s: np.ndarray, setup: LMSetup, x0: np.ndarra
     ev = _ev(events)
     x = np.array(x0, dtype=np.float64).reshape(geom.shape)
     m = np.ones(len(ev)) if setup.m is None else setup.m
-    y = 1.0 - setup.mu / (m * fwd(geom, x, ev) + s)
+    y = 1.0 - setup.mu / (_fwd_model(geom, setup, x, ev, m) + s)
     w = np.zeros((3,) + geom.shape)
-    z = setup.g + back(geom, m * (y - 1.0) / setup.mu, ev) + k_adj(w, setup.xi)
+    z = setup.g + _back_model(geom, setup, (y - 1.0) / setup.mu, ev, m) + k_adj(w, setup.xi)
     return LMState(x=x, z=z, zbar=z.copy(), w=w, y=y, u=0)
 
 
@@ -419,10 +469,10 @@ def lm_update(geom: Geometry, events, s: np.ndarray, setup: LMSetup, st: LMState
     if i < n_subsets:
         e = setup.subsets[i]
         me = 1.0 if setup.m is None else setup.m[e]
-        q = me * fwd(geom, st.x, ev[e]) + s[e]
+        q = _fwd_model(geom, setup, st.x, ev[e], me) + s[e]
         a = st.y[e] + setup.S[e] * q
         yp = prox_poisson_dual(a, setup.S[e], setup.mu[e])
-        dz = back(geom, me * (yp - st.y[e]) / setup.mu[e], ev[e])
+        dz = _back_model(geom, setup, (yp - st.y[e]) / setup.mu[e], ev[e], me)
         st.y[e] = yp
         p = 1.0 / (2.0 * n_subsets)
     else:
@@ -442,13 +492,14 @@ def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarra
              knorm: Optional[float] = None, state: Optional[LMState] = None,
              setup: Optional[LMSetup] = None,
              callback: Optional[Callable[[LMState, LMSetup], None]] = None,
-             xi: Optional[np.ndarray] = None, m: Optional[np.ndarray] = None):
+             xi: Optional[np.ndarray] = None, m: Optional[np.ndarray] = None,
+             fwhm: Optional[Sequence[float]] = None):
     """Run the updates listed in ``seq`` (each entry a subset index, or
     n_subsets for the prior) and return (x, state, setup).  x is the image of
     the last x-update (the value Algorithm 2 returns)."""
     s = np.asarray(s, dtype=np.float64)
     if setup is None:
-        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm, xi, m)
+        setup = lm_setup(geom, events, n_subsets, np.asarray(g, dtype=np.float64), gamma, rho, knorm, xi, m, fwhm)
     if state is None:
         state = lm_init(geom, events, s, setup, x0)
     for i in seq:
