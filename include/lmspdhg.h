@@ -196,6 +196,21 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq_host, int32_t n_upda
  * positive and finite (nothing changed). */
 int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream);
 
+/* Image-space resolution model (Section 1: P includes limited spatial
+ * resolution): the plan's operator becomes G B, G the projector, B a
+ * separable Gaussian convolution with FWHM fwhm_vox[a] voxels along x, y, z
+ * (host array; 0 leaves an axis alone, all 0 removes the model).  Taps are
+ * truncated at ceil(3 sigma) voxels (at most 16) and normalised to sum 1;
+ * outside the image counts as zero, so B is symmetric and the back
+ * projection is B G^T.  Each data update then blurs x before its
+ * projections and blurs its back projection before the z step: four more
+ * images of plan memory and two passes per blurred axis.  P^LM 1 and S_e are
+ * recomputed for G B; the g given to lm_plan_create must be the sensitivity
+ * of the whole operator.  Synchronous.  Before lm_spdhg_init or
+ * lm_plan_set_state (LM_ESTATE otherwise); LM_EINVAL for a negative FWHM or
+ * one beyond 16 taps of radius. */
+int lm_plan_set_resolution(lm_plan *p, const double fwhm_vox[3], void *stream);
+
 /* Directional TV prior (Section 3, DTV; Ehrhardt & Betcke 2016) in place of
  * TV: K = D grad with D_j = I - xi_j xi_j^T, which removes from each
  * voxel's finite-difference vector its component along the normalised

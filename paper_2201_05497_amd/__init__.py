@@ -268,6 +268,13 @@ class Plan:
         _lib.check(_L.lm_plan_set_event_factors(self._handle(), m.data_ptr(), _stream(self.geom.device)),
                    "lm_plan_set_event_factors")
 
+    def set_resolution(self, fwhm_vox) -> None:
+        """Image-space resolution model: the operator becomes G B with B a
+        separable Gaussian of FWHM fwhm_vox = (fx, fy, fz) voxels.  Before
+        init; g must be the sensitivity of G B."""
+        f = (ctypes.c_double * 3)(*[float(v) for v in fwhm_vox])
+        _lib.check(_L.lm_plan_set_resolution(self._handle(), f, _stream(self.geom.device)), "lm_plan_set_resolution")
+
     def set_prior_image(self, v: Optional[torch.Tensor], eta: float = 0.0) -> None:
         """Directional TV: later prior updates use K = D grad with the
         normalised gradient of the prior image v (eta > 0); None: TV."""

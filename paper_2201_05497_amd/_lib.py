@@ -43,6 +43,7 @@ SIGNATURES = {
     "lm_spdhg_epoch": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_int32), _I32, _VP]),
     "lm_plan_set_prior_image": (ctypes.c_int, [_VP, _VP, _D, _VP]),
     "lm_plan_set_event_factors": (ctypes.c_int, [_VP, _VP, _VP]),
+    "lm_plan_set_resolution": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "lm_plan_info": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int64)]),
     "lm_plan_get_lists": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),

@@ -1,0 +1,86 @@
+// Image-space resolution model (Section 1: the forward model includes
+// limited spatial resolution): P = G B with B a separable Gaussian
+// convolution, zero outside the image, so that B is symmetric and the back
+// projection applies the same B after G^T.  One pass per blurred axis over
+// the plan's bricked images; each voxel reads 2 r + 1 neighbours along the
+// axis (L2 hits) and writes one value: bound by HBM bandwidth.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lm_blur.hpp"
+#include "lm_host.hpp"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+__global__ __launch_bounds__(kBlock) void k_blur_axis(const float *__restrict__ in, float *__restrict__ out,
+                                                      lmk::Layout L, int nx, int ny, int nz, long long ne, int axis,
+                                                      lmk::BlurAxis taps) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= ne) return;
+  int c[3];
+  lmk::vpos(L, p, c[0], c[1], c[2]);
+  if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding
+  const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
+  const int c0 = c[axis];
+  float acc = 0.0f;
+  for (int t = -taps.r; t <= taps.r; ++t) {
+    const int q = c0 + t;
+    if (q < 0 || q >= n) continue;
+    c[axis] = q;
+    acc = fmaf(taps.w[t + taps.r], in[lmk::vidx(L, c[0], c[1], c[2])], acc);
+  }
+  out[p] = acc;
+}
+
+}  // namespace
+
+namespace lmk {
+
+int make_blur(const double fwhm[3], Blur *b) {
+  b->on = false;
+  for (int a = 0; a < 3; ++a) {
+    BlurAxis &ax = b->ax[a];
+    ax.r = 0;
+    for (float &w : ax.w) w = 0.0f;
+    const double f = fwhm[a];
+    LM_REQUIRE(f >= 0.0 && std::isfinite(f), LM_EINVAL, "FWHM along axis %d must be finite and >= 0", a);
+    if (f == 0.0) continue;
+    const double sig = f / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const int r = (int)std::ceil(3.0 * sig);
+    LM_REQUIRE(r <= kMaxBlurRadius, LM_EINVAL, "FWHM %.3g voxels along axis %d exceeds the largest supported (%d taps)",
+               f, a, 2 * kMaxBlurRadius + 1);
+    double w[2 * kMaxBlurRadius + 1], sum = 0.0;
+    for (int t = -r; t <= r; ++t) sum += (w[t + r] = std::exp(-(double)t * t / (2.0 * sig * sig)));
+    for (int t = -r; t <= r; ++t) ax.w[t + r] = (float)(w[t + r] / sum);
+    ax.r = r;
+    b->on = true;
+  }
+  return LM_OK;
+}
+
+int launch_blur(const int n[3], const Layout &L, long long ne, const Blur &b, const float *in, float *out, float *t1,
+                float *t2, hipStream_t st) {
+  int axes[3], na = 0;
+  for (int a = 0; a < 3; ++a)
+    if (b.ax[a].r > 0) axes[na++] = a;
+  if (na == 0) {
+    LM_TRY_HIP(hipMemcpyAsync(out, in, (size_t)ne * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return LM_OK;
+  }
+  const float *src = in;
+  for (int k = 0; k < na; ++k) {
+    float *dst = k + 1 == na ? out : (k % 2 == 0 ? t1 : t2);
+    hipLaunchKernelGGL(k_blur_axis, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2], ne,
+                       axes[k], b.ax[axes[k]]);
+    LM_TRY_HIP(hipGetLastError());
+    src = dst;
+  }
+  return LM_OK;
+}
+
+}  // namespace lmk

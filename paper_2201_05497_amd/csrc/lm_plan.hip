@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "lm_blur.hpp"
 #include "lm_device.hpp"
 #include "lm_dtv.hpp"
 #include "lm_host.hpp"
@@ -78,6 +79,10 @@ struct lm_plan {
   // per-event multiplicative factors (lm_plan_set_event_factors), sorted
   // order; folded into s and mu, kept to return the event counts
   float *mfac = nullptr;
+  // resolution model (lm_plan_set_resolution): B x for the data updates,
+  // B dz after them, and two temporaries of the separable passes
+  lmk::Blur blur{};
+  float *xb = nullptr, *dzb = nullptr, *bt1 = nullptr, *bt2 = nullptr;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
@@ -203,6 +208,12 @@ __global__ void k_scatter_mu(const float *in, const int *perm, int *out, long lo
 __global__ void k_scatter_mu_fac(const float *in, const float *m, const int *perm, int *out, long long n) {
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) out[perm[j]] = (int)rintf(in[j] * m[j]);
+}
+
+// z += a
+__global__ void k_add(float *z, const float *a, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] += a[i];
 }
 
 // Counts factors that are not positive and finite.
@@ -485,11 +496,23 @@ int lm_spdhg_init(lm_plan *p, const float *x0, void *stream) {
   const long long N = p->n, E = p->ne;
   if (int rc = lmk::launch_to_layout(p->G.n, p->lay, 1, x0, p->xint, st)) return rc;
   LM_TRY_HIP(hipMemcpyAsync(p->z, p->gimg, E * sizeof(float), hipMemcpyDeviceToDevice, st));
-  if (N > 0) {
+  if (N > 0 && !p->blur.on) {
     if (int rc = lmk::launch_fwd_rec(p->g, p->xint, p->rec, N, p->c, st)) return rc;
     hipLaunchKernelGGL(k_init_dual, dim3(grid_for(N)), dim3(kBlock), 0, st, p->c, p->rec, p->mu, p->tmp, N);
     LM_TRY_HIP(hipGetLastError());
     if (int rc = lmk::launch_back_rec(p->g, p->tmp, p->rec, N, p->z, st)) return rc;
+  } else if (N > 0) {
+    // P = G B: y from G (B x0); z gains B G^T((y - 1) / mu)
+    if (int rc = lmk::launch_blur(p->G.n, p->lay, E, p->blur, p->xint, p->xb, p->bt1, p->bt2, st)) return rc;
+    if (int rc = lmk::launch_fwd_rec(p->g, p->xb, p->rec, N, p->c, st)) return rc;
+    hipLaunchKernelGGL(k_init_dual, dim3(grid_for(N)), dim3(kBlock), 0, st, p->c, p->rec, p->mu, p->tmp, N);
+    LM_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, p->dz, 0.0f, E);
+    LM_TRY_HIP(hipGetLastError());
+    if (int rc = lmk::launch_back_rec(p->g, p->tmp, p->rec, N, p->dz, st)) return rc;
+    if (int rc = lmk::launch_blur(p->G.n, p->lay, E, p->blur, p->dz, p->dzb, p->bt1, p->bt2, st)) return rc;
+    hipLaunchKernelGGL(k_add, dim3(grid_for(E)), dim3(kBlock), 0, st, p->z, p->dzb, E);
+    LM_TRY_HIP(hipGetLastError());
   }
   LM_TRY_HIP(hipMemcpyAsync(p->zbar, p->z, E * sizeof(float), hipMemcpyDeviceToDevice, st));
   LM_TRY_HIP(hipMemsetAsync(p->w, 0, E * p->ncomp * sizeof(float), st));
@@ -524,14 +547,32 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
     const bool fuse = u + 1 < n_updates;
     if (i < p->nsub) {
       const long long o = p->off[i], c = p->off[i + 1] - p->off[i];
-      if (int rc = timed(p, LM_K_DATA, st, [&] {
-            return lmk::launch_data_update(p->g, xi, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz, c, st);
-          }))
-        return rc;
-      if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
-            return lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
-          }))
-        return rc;
+      if (!p->blur.on) {
+        if (int rc = timed(p, LM_K_DATA, st, [&] {
+              return lmk::launch_data_update(p->g, xi, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz, c, st);
+            }))
+          return rc;
+        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
+              return lmk::launch_dual_image(p->z, p->dz, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
+            }))
+          return rc;
+      } else {
+        // P = G B: the update projects B x; z takes B of its back projection
+        if (int rc = timed(p, LM_K_DATA, st, [&] {
+              int r = lmk::launch_blur(p->G.n, p->lay, E, p->blur, xi, p->xb, p->bt1, p->bt2, st);
+              return r ? r : lmk::launch_data_update(p->g, p->xb, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz,
+                                                     c, st);
+            }))
+          return rc;
+        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&]() -> int {
+              int r = lmk::launch_blur(p->G.n, p->lay, E, p->blur, p->dz, p->dzb, p->bt1, p->bt2, st);
+              if (r) return r;
+              hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, p->dz, 0.0f, E);
+              LM_TRY_HIP(hipGetLastError());
+              return lmk::launch_dual_image(p->z, p->dzb, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
+            }))
+          return rc;
+      }
     } else if (p->dtv) {
       // K = D grad: the dual step, then the adjoint fused with z / zbar and
       // the next primal step (in place)
@@ -582,6 +623,42 @@ int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream) {
   if (int rc = dalloc(p, &p->mfac, (size_t)N)) return rc;
   hipLaunchKernelGGL(k_apply_factors, dim3(grid_for(N)), dim3(kBlock), 0, st, m, p->perm, p->rec, p->mu, p->mfac, N);
   LM_TRY_HIP(hipGetLastError());
+  LM_TRY_HIP(hipStreamSynchronize(st));
+  return LM_OK;
+}
+
+int lm_plan_set_resolution(lm_plan *p, const double fwhm_vox[3], void *stream) {
+  lmh::clear_error();
+  LM_REQUIRE(p && fwhm_vox, LM_EINVAL, "NULL plan or FWHM");
+  LM_REQUIRE(!p->initialized, LM_ESTATE, "the resolution model must be set before lm_spdhg_init");
+  lmk::Blur b;
+  if (int rc = lmk::make_blur(fwhm_vox, &b)) return rc;
+  hipStream_t st = lmh::as_stream(stream);
+  p->last = st;
+  const long long N = p->n, E = p->ne;
+  if (b.on && !p->xb) {
+    int rc;
+    if ((rc = dalloc(p, &p->xb, (size_t)E)) || (rc = dalloc(p, &p->dzb, (size_t)E)) ||
+        (rc = dalloc(p, &p->bt1, (size_t)E)) || (rc = dalloc(p, &p->bt2, (size_t)E)))
+      return rc;
+  }
+  p->blur = b;
+  // P^LM 1 and S_e = gamma rho / (P^LM 1)_e of the operator G B
+  if (N > 0) {
+    float *ones = b.on ? p->dzb : p->dz;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, ones, 1.0f, E);
+    LM_TRY_HIP(hipGetLastError());
+    const float *src = ones;
+    if (b.on) {
+      if (int rc = lmk::launch_blur(p->G.n, p->lay, E, b, ones, p->xb, p->bt1, p->bt2, st)) return rc;
+      src = p->xb;
+    }
+    if (int rc = lmk::launch_fwd_rec(p->g, src, p->rec, N, p->P1, st)) return rc;
+    hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(p->gamma * p->rho), N);
+    LM_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, ones, 0.0f, E);
+    LM_TRY_HIP(hipGetLastError());
+  }
   LM_TRY_HIP(hipStreamSynchronize(st));
   return LM_OK;
 }

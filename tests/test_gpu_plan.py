@@ -96,7 +96,7 @@ def test_preprocessing_2d(P):
 
 
 def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=None, s=None, gamma=None,
-                 rho=RHO, xi=None, m=None):
+                 rho=RHO, xi=None, m=None, fwhm=None):
     Go = oracle.Geometry.from_problem(p)
     ev = p.events if events is None else events
     ss = (p.s if s is None else s).astype(np.float64)
@@ -110,7 +110,7 @@ def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=
         plan.epoch(x, seq)
         x_o, st, su = oracle.lm_spdhg(Go, ev, ss, g_orc, p.x0, n_sub, seq,
                                       _gamma(p.x0) if gamma is None else gamma, rho, beta, state=st, setup=su,
-                                      xi=xi, m=m)
+                                      xi=xi, m=m, fwhm=fwhm)
         e = img_err(x.cpu().numpy(), x_o)
         errs.append(e)
         report(f"{name} epoch {ep + 1}", x_err=e)
@@ -175,6 +175,33 @@ def test_event_factors_2d(P):
     with pytest.raises(P.LMError):
         plan2.set_event_factors(torch.as_tensor(bad, device="cuda"))
     plan2.set_event_factors(torch.as_tensor(m, device="cuda"))  # nothing was changed by the refused call
+
+
+def test_resolution_model_2d(P):
+    """The forward model G B with a Gaussian resolution model (FWHM 2.5 x 2
+    voxels in plane) and per-event factors on the 2D workload: P^LM 1 of
+    G B and 3 epochs against the oracle; bad FWHMs and a call after init
+    are rejected."""
+    p = problem_2d()
+    c1, c2 = p.events[:, 0].astype(np.float64), p.events[:, 2].astype(np.float64)
+    m = (0.5 + 0.4 * np.cos(0.23 * (c1 + c2)) ** 2).astype(np.float32)
+    fwhm = (2.5, 2.0, 0.0)
+    g = sens_2d()
+    Gg, plan = _plan(P, p, 28, g, 0.03)
+    for bad in ((-1.0, 0.0, 0.0), (0.0, 60.0, 0.0)):
+        with pytest.raises(P.LMError):
+            plan.set_resolution(bad)
+    plan.set_event_factors(torch.as_tensor(m, device="cuda"))
+    plan.set_resolution(fwhm)
+    Go = oracle.Geometry.from_problem(p)
+    _, _, _, p1 = plan.lists()
+    emax, _ = proj_err(p1.cpu().numpy(), oracle.fwd(Go, oracle.blur(np.ones(Go.shape), fwhm), p.events))
+    report("2d resolution model P^LM 1", p1_max=emax)
+    assert emax <= PROJ_TOL
+    _run_compare(P, p, Gg, plan, g.astype(np.float32).astype(np.float64), 28, 0.03, 3, 2007, "2d resolution",
+                 m=m.astype(np.float64), fwhm=fwhm)
+    with pytest.raises(P.LMError):
+        plan.set_resolution(fwhm)
 
 
 def test_dtv_prior_2d(P):
@@ -464,15 +491,16 @@ def test_prior_updates_ragged_grids(P, shape):
     assert ex <= ITER_TOL and ez <= ITER_TOL and ew <= ITER_TOL
 
 
-@pytest.mark.parametrize("shape,dtv", [((37, 29, 11), False), ((20, 33, 18), False), ((37, 29, 11), True),
-                                       ((20, 33, 18), True)])
-def test_mixed_updates_ragged_grids(P, shape, dtv):
+@pytest.mark.parametrize("shape,dtv,fwhm", [((37, 29, 11), False, None), ((20, 33, 18), False, None),
+                                            ((37, 29, 11), True, None), ((20, 33, 18), True, None),
+                                            ((20, 33, 18), False, (1.5, 2.0, 1.2))])
+def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm):
     """Mixed data and prior updates from a random state on ragged 3D grids,
     over two calls, against the oracle: data updates followed by prior
     updates and by data updates, prior updates in a row, and calls that end
     with either kind (the last update of a call materialises zbar instead
-    of fusing the next primal step); with the TV prior and with the DTV
-    prior of a smooth structural image."""
+    of fusing the next primal step); with the TV prior, with the DTV prior
+    of a smooth structural image, and with a resolution model."""
     nx, ny, nz = shape
     sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
     tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
@@ -492,7 +520,7 @@ def test_mixed_updates_ragged_grids(P, shape, dtv):
     Go = oracle.Geometry.from_problem(p)
     v, eta = smooth_image(zyx, 79, base=2.0), 0.05
     xi = oracle.dtv_field(v.astype(np.float64), eta) if dtv else None
-    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO, xi=xi)
+    su = oracle.lm_setup(Go, p.events, n, g.astype(np.float64), _gamma(p.x0), RHO, xi=xi, fwhm=fwhm)
     st = oracle.LMState(x=x_start.astype(np.float64), z=z0.astype(np.float64), zbar=zb0.astype(np.float64),
                         w=w0.astype(np.float64), y=1.0 - c0.astype(np.float64), u=0)
     calls = [np.array([0, 4, 4, 1, 4, 2, 3, 4, 0, 4], np.int32), np.array([4, 1, 4, 2, 2, 4, 3, 4], np.int32)]
@@ -500,6 +528,8 @@ def test_mixed_updates_ragged_grids(P, shape, dtv):
     cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
     if dtv:
         plan.set_prior_image(cuda(v), eta)
+    if fwhm is not None:
+        plan.set_resolution(fwhm)
     plan.set_state({"z": cuda(z0), "zbar": cuda(zb0), "w": cuda(w0), "c": cuda(c0), "u": 0})
     x = cuda(x_start)
     for k, seq in enumerate(calls):
@@ -513,5 +543,5 @@ def test_mixed_updates_ragged_grids(P, shape, dtv):
         ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
         wg = state["w"].cpu().numpy().astype(np.float64)
         ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
-        report(f"mixed updates {shape} dtv={dtv} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
+        report(f"mixed updates {shape} dtv={dtv} fwhm={fwhm} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
         assert max(ex, ez, ezb, ec, ew) <= ITER_TOL
