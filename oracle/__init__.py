@@ -30,7 +30,14 @@ Readings of the paper taken here, where it is silent or ambiguous:
   with the full projection D and the same ||grad|| as the norm bound;
 * T = min over the subset step sizes and the prior step size:
   T_j = rho / (2 gamma max(g_j, ||K||)) with p_k = 1/(2n), p_prior = 1/2;
-  S_e = gamma rho / (P^LM 1)_e, and 0 where (P^LM 1)_e = 0.
+  S_e = gamma rho / (P^LM 1)_e, and 0 where (P^LM 1)_e = 0;
+* attenuation and normalisation (inside P, Section 1) are one factor per
+  event's LOR, P' = diag(m) P; limited resolution is an image-space
+  separable Gaussian B with a zero boundary, P = G B; the sensitivity g of
+  the whole operator is an input.
+
+The readings of the EM-TV warm start and of the DTV prior are listed with
+their code below.
 """
 from __future__ import annotations
 

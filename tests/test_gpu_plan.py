@@ -2,7 +2,8 @@
 event counts, subsets and layout (bit-exact), step sizes, initialisation
 and the iterates of Algorithm 2 after every epoch (||gpu - orc||_inf <=
 1e-4 ||orc||_inf), plus checkpoint/resume, error paths and degenerate
-inputs."""
+inputs; the DTV prior, per-event attenuation x normalisation factors, the
+resolution model and the accelerated parameters (rho = 8)."""
 import functools
 
 import numpy as np
