@@ -72,3 +72,30 @@ def test_invalid_image_size_rejected(lib):
     assert L.lm_plan_destroy(None) == 0
     n3 = (ctypes.c_int32 * 3)(0, 1, 1)
     assert L.tv_grad(n3, 0x1000, 0x1000, None) == lib.LM_EINVAL
+
+
+def test_new_entry_points_check_arguments_first(lib):
+    """lm_emtv and the plan's model setters reject bad arguments before any
+    device work (the pointers below are never dereferenced)."""
+    L = lib.load()
+    g = _geom(lib)
+    P_ = 0x1000
+    # lm_emtv(G, ev, s, n, n_subsets, n_iter, g, beta, denoise_iter, x, stream)
+    for args in ((P_, P_, 10, 0, 1, P_, 0.03, 20, P_),      # no subsets
+                 (P_, P_, -1, 4, 1, P_, 0.03, 20, P_),      # negative count
+                 (P_, P_, 10, 4, -1, P_, 0.03, 20, P_),     # negative iterations
+                 (P_, P_, 10, 4, 1, P_, 0.03, -5, P_),      # negative denoising steps
+                 (P_, P_, 10, 4, 1, P_, -0.1, 20, P_),      # negative beta
+                 (P_, P_, 10, 4, 1, P_, float("nan"), 20, P_),
+                 (P_, P_, 10, 4, 1, None, 0.03, 20, P_),    # no sensitivity image
+                 (None, P_, 10, 4, 1, P_, 0.03, 20, P_)):   # no events
+        assert L.lm_emtv(ctypes.byref(g), *args, None) == lib.LM_EINVAL, args
+        assert len(L.lm_last_error()) > 0
+    bad = _geom(lib, n=(0, 4, 4))
+    assert L.lm_emtv(ctypes.byref(bad), P_, P_, 10, 4, 1, P_, 0.03, 20, P_, None) == lib.LM_EINVAL
+    # no iterations: nothing to do
+    assert L.lm_emtv(ctypes.byref(g), P_, P_, 10, 4, 0, P_, 0.03, 20, P_, None) == 0
+    f3 = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert L.lm_plan_set_prior_image(None, P_, 0.1, None) == lib.LM_EINVAL
+    assert L.lm_plan_set_event_factors(None, P_, None) == lib.LM_EINVAL
+    assert L.lm_plan_set_resolution(None, f3, None) == lib.LM_EINVAL
