@@ -136,7 +136,9 @@ typedef struct lm_plan lm_plan;
 
 /* Device bytes a plan for n_ev events and n_sub subsets will allocate,
  * including the temporary memory of lm_plan_create; host output *bytes.
- * Used to admit reconstructions against an HBM budget. */
+ * Used to admit reconstructions against an HBM budget.  The optional parts
+ * (lm_plan_set_prior_image, lm_plan_set_event_factors,
+ * lm_plan_set_resolution) allocate more, as each of them states. */
 int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes);
 
 /* Synchronous.  Builds a plan: copies and validates the events (LM_ERANGE
