@@ -49,6 +49,39 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis(const float *__restrict__ 
   out[p] = acc;
 }
 
+// The last blur pass of a data update's back projection fused with the z
+// step: d = (blur along `axis` of src)_p, z += d, zbar = z + d inv_p,
+// fuse ? x = max(0, x - T zbar) : store zbar, and dz = 0 for the next
+// update's atomics (dz is not read by this pass: src is a temporary).
+__global__ __launch_bounds__(kBlock) void k_blur_axis_dual(const float *__restrict__ src, float *__restrict__ dz,
+                                                           float *__restrict__ z, float *__restrict__ x,
+                                                           const float *__restrict__ T, float *__restrict__ zbar,
+                                                           float inv_p, int fuse, lmk::Layout L, int nx, int ny,
+                                                           int nz, long long ne, int axis, lmk::BlurAxis taps) {
+  const unsigned p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= ne) return;
+  int c[3];
+  vpos32(L, p, c[0], c[1], c[2]);
+  if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding (stays zero)
+  const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
+  const int c0 = c[axis];
+  float d = 0.0f;
+  for (int t = -taps.r; t <= taps.r; ++t) {
+    const int q = c0 + t;
+    if (q < 0 || q >= n) continue;
+    c[axis] = q;
+    d = fmaf(taps.w[t + taps.r], src[lmk::vidx(L, c[0], c[1], c[2])], d);
+  }
+  const float zn = z[p] + d;
+  const float zb = fmaf(d, inv_p, zn);
+  z[p] = zn;
+  if (fuse)
+    x[p] = fmaxf(0.0f, fmaf(-T[p], zb, x[p]));
+  else
+    zbar[p] = zb;
+  dz[p] = 0.0f;
+}
+
 }  // namespace
 
 namespace lmk {
@@ -92,6 +125,39 @@ int launch_blur(const int n[3], const Layout &L, long long ne, const Blur &b, co
     LM_TRY_HIP(hipGetLastError());
     src = dst;
   }
+  return LM_OK;
+}
+
+int launch_blur_dual_image(const int n[3], const Layout &L, long long ne, const Blur &b, float *dz, float *t1,
+                           float *t2, float *z, float *x, const float *T, float *zbar, float inv_p, bool fuse,
+                           hipStream_t st) {
+  int axes[3], na = 0;
+  for (int a = 0; a < 3; ++a)
+    if (b.ax[a].r > 0) axes[na++] = a;
+  LM_REQUIRE(na > 0, LM_EINVAL, "no blurred axis");
+  // all passes but the last; with one blurred axis that pass goes to t1
+  // and the fused pass applies the identity (it must not read dz)
+  const float *src = dz;
+  const int plain = na == 1 ? 1 : na - 1;
+  for (int k = 0; k < plain; ++k) {
+    float *dst = k % 2 == 0 ? t1 : t2;
+    hipLaunchKernelGGL(k_blur_axis, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2], ne,
+                       axes[k], b.ax[axes[k]]);
+    LM_TRY_HIP(hipGetLastError());
+    src = dst;
+  }
+  BlurAxis last{};
+  int axis = 0;
+  if (na == 1) {
+    last.r = 0;
+    last.w[0] = 1.0f;
+  } else {
+    axis = axes[na - 1];
+    last = b.ax[axis];
+  }
+  hipLaunchKernelGGL(k_blur_axis_dual, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dz, z, x, T, zbar, inv_p,
+                     fuse ? 1 : 0, L, n[0], n[1], n[2], ne, axis, last);
+  LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
 

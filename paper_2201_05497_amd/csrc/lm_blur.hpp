@@ -29,4 +29,12 @@ int make_blur(const double fwhm[3], Blur *b);
 int launch_blur(const int n[3], const Layout &L, long long ne, const Blur &b, const float *in, float *out, float *t1,
                 float *t2, hipStream_t st);
 
+// The z step of Algorithm 2 after a data update under the resolution
+// model: dzb = B dz, z += dzb, zbar = z + dzb inv_p, fuse ? x = max(0, x -
+// T zbar) (in place) : store zbar, and dz = 0.  The last blur pass carries
+// the z step; t1, t2 are temporaries of ne elements.
+int launch_blur_dual_image(const int n[3], const Layout &L, long long ne, const Blur &b, float *dz, float *t1,
+                           float *t2, float *z, float *x, const float *T, float *zbar, float inv_p, bool fuse,
+                           hipStream_t st);
+
 }  // namespace lmk

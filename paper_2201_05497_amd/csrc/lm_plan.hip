@@ -564,12 +564,9 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
                                                      c, st);
             }))
           return rc;
-        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&]() -> int {
-              int r = lmk::launch_blur(p->G.n, p->lay, E, p->blur, p->dz, p->dzb, p->bt1, p->bt2, st);
-              if (r) return r;
-              hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, p->dz, 0.0f, E);
-              LM_TRY_HIP(hipGetLastError());
-              return lmk::launch_dual_image(p->z, p->dzb, xi, p->T, p->zbar, inv_p_data, fuse, E, st);
+        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
+              return lmk::launch_blur_dual_image(p->G.n, p->lay, E, p->blur, p->dz, p->bt1, p->bt2, p->z, xi, p->T,
+                                                 p->zbar, inv_p_data, fuse, st);
             }))
           return rc;
       }

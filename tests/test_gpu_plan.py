@@ -494,7 +494,8 @@ def test_prior_updates_ragged_grids(P, shape):
 
 @pytest.mark.parametrize("shape,dtv,fwhm", [((37, 29, 11), False, None), ((20, 33, 18), False, None),
                                             ((37, 29, 11), True, None), ((20, 33, 18), True, None),
-                                            ((20, 33, 18), False, (1.5, 2.0, 1.2))])
+                                            ((20, 33, 18), False, (1.5, 2.0, 1.2)),
+                                            ((37, 29, 11), False, (0.0, 0.0, 1.5))])
 def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm):
     """Mixed data and prior updates from a random state on ragged 3D grids,
     over two calls, against the oracle: data updates followed by prior
