@@ -13,6 +13,12 @@
 //
 // Subsets are interleaved (event e goes to subset e mod n); the plan stores
 // the events of each subset contiguously so one launch streams one subset.
+//
+// Optional parts of the model, set before the initialisation (or, for the
+// prior, at any time): per-event attenuation x normalisation factors, folded
+// exactly into the stored s and mu; an image-space resolution model B
+// (x blurred before each data update, its back projection after); the
+// directional TV prior in place of TV.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
