@@ -83,13 +83,21 @@ int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n,
 int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img,
                 hipStream_t st);
 int launch_sens(const GeomDev &g, float *img, hipStream_t st);
-// Sensitivity by transaxial line (lm_lines.hip) for cylindrical 3D
-// scanners; `done` is false when the geometry does not qualify.
-int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done);
-// Back projection of a long event list by transaxial line (lm_lines.hip);
-// `done` is false when the geometry or the list does not qualify.
-int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st,
-                      bool &done);
+// Paths by transaxial line (lm_lines.hip) for cylindrical 3D scanners.
+// lines_possible: the host-side part of the test (at least two rings and
+// crystals); launch_cylindrical writes the rest of it to a device flag
+// (1: crystal c of ring r at (x_c, y_c, z_r), z increasing with r), which
+// the line kernels and the per-event fallback read, so that choosing the
+// path never synchronises the stream.
+bool lines_possible(const GeomDev &g);
+int launch_cylindrical(const GeomDev &g, int *flag, hipStream_t st);
+// Sensitivity by line: nothing happens unless *cyl.
+int launch_sens_lines(const GeomDev &g, const int *cyl, float *img, hipStream_t st);
+// Back projection of a long event list by line, guarded by *cyl; `queued`
+// is false (nothing enqueued) when the list is too short or the
+// temporaries of the sort do not fit.
+int launch_back_lines(const GeomDev &g, const int *cyl, const float *v, const int16_t *ev, long long n, float *img,
+                      hipStream_t st, bool &queued);
 // Plan-internal event records: int4 {id1, id2, k, s bits}.
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
                    hipStream_t st);
@@ -100,3 +108,32 @@ int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long
 int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const float *S,
                        const float *mu, float *cdual, float *dz, long long n, hipStream_t st);
 }  // namespace lmk
+
+namespace lmh {
+
+// The plain projector calls run on a bricked copy of the caller's row-major
+// image (the layout of the plans, 4x4x4 voxels per brick): gathers and the
+// interleaved scatter then touch few cache lines per instruction.  The copy
+// is a stream-ordered temporary freed (stream-ordered) when the call
+// returns; its padding voxels are never read or written, since every
+// corner is checked against the image size.
+struct BrickImage {
+  float *p = nullptr;
+  hipStream_t st = nullptr;
+  int alloc(lmk::GeomDev &g, hipStream_t s) {
+    g.lay = lmh::brick_layout(g.n);
+    st = s;
+    const hipError_t e = hipMallocAsync((void **)&p, (size_t)lmk::layout_size(g.lay) * sizeof(float), s);
+    if (e != hipSuccess) {
+      p = nullptr;
+      lmh::set_error("image temporary: %s", hipGetErrorString(e));
+      return LM_ENOMEM;
+    }
+    return LM_OK;
+  }
+  ~BrickImage() {
+    if (p) (void)hipFreeAsync(p, st);  // a release error has no caller to go to
+  }
+};
+
+}  // namespace lmh

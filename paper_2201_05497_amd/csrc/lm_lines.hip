@@ -211,9 +211,10 @@ constexpr int kZPart = 16;
 // Block b (one wavefront): line b / (nchunk nzp), planes 64 chunk .. + 63
 // with chunk = (b / nzp) % nchunk, and z part b % nzp.  A LOR whose z range
 // over the chunk's planes misses the part is skipped on uniform values.
-__global__ __launch_bounds__(kLanes) void k_sens_lines(GeomDev g, long long p0, long long nlines, int nchunk,
-                                                       int nzp, float *img) {
+__global__ __launch_bounds__(kLanes) void k_sens_lines(GeomDev g, const int *cyl, long long p0, long long nlines,
+                                                       int nchunk, int nzp, float *img) {
   __shared__ float acc[2 * kZPart * kLanes];
+  if (!*cyl) return;
   const long long blk = (long long)blockIdx.x;
   const long long per_line = (long long)nchunk * nzp;
   if (blk / per_line >= nlines) return;
@@ -311,8 +312,10 @@ struct Stage1 {
 // dominant axis is z.  Block p: crystals c1 <= c2 (the pair index of the
 // upper triangle with its diagonal); ring pairs (r1, r2) for c1 < c2 and
 // r1 < r2 for c1 = c2.
-__global__ __launch_bounds__(kLanes) void k_sens_zdom(GeomDev g, long long p0, long long np, float *img) {
+__global__ __launch_bounds__(kLanes) void k_sens_zdom(GeomDev g, const int *cyl, long long p0, long long np,
+                                                      float *img) {
   __shared__ Stage1 st;
+  if (!*cyl) return;
   const long long q = (long long)blockIdx.x;
   if (q >= np) return;
   const int lane = threadIdx.x;
@@ -394,10 +397,10 @@ __device__ __forceinline__ int event_line(const GeomDev &g, const int16_t *e, fl
 
 // Line of every event and its rank among its line's events (in no fixed
 // order: the rank comes from an atomic counter per line).
-__global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int16_t *ev, const float *v, long long n,
-                                                   int *key, unsigned *rank, unsigned *cnt) {
+__global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int *cyl, const int16_t *ev, const float *v,
+                                                   long long n, int *key, unsigned *rank, unsigned *cnt) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
+  if (e >= n || !*cyl) return;
   unsigned rk;
   const int L = event_line(g, ev + 5 * e, v[e], rk);
   key[e] = L;
@@ -406,8 +409,10 @@ __global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int16_t *ev,
 
 // Exclusive prefix sum of cnt[0 .. n) into off[0 .. n]; one block of 1024
 // threads, each summing a contiguous segment.
-__global__ __launch_bounds__(1024) void k_line_offsets(const unsigned *cnt, long long n, unsigned *off) {
+__global__ __launch_bounds__(1024) void k_line_offsets(const int *cyl, const unsigned *cnt, long long n,
+                                                       unsigned *off) {
   __shared__ unsigned part[1024];
+  if (!*cyl) return;
   const int t = threadIdx.x;
   const long long seg = (n + 1023) / 1024;
   const long long a = min(n, t * seg), b = min(n, a + seg);
@@ -429,11 +434,11 @@ __global__ __launch_bounds__(1024) void k_line_offsets(const unsigned *cnt, long
   if (t == 1023) off[n] = part[1023];
 }
 
-__global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int16_t *ev, const float *v, long long n,
-                                                    const int *key, const unsigned *rank, const unsigned *off,
-                                                    LineRec *rec) {
+__global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int *cyl, const int16_t *ev, const float *v,
+                                                    long long n, const int *key, const unsigned *rank,
+                                                    const unsigned *off, LineRec *rec) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
+  if (e >= n || !*cyl) return;
   const int L = key[e];
   if (L < 0) return;
   unsigned rk;
@@ -447,10 +452,11 @@ __global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int16_t *ev
 // Back projection of the events of every line (records rec[off[L] ..
 // off[L+1])); blocks as in k_sens_lines.  An event is skipped on uniform
 // values when its TOF window or its z range misses the chunk and part.
-__global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned *off, const LineRec *rec,
-                                                       long long p0, long long nlines, int nchunk, int nzp,
-                                                       float *img) {
+__global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const int *cyl, const unsigned *off,
+                                                       const LineRec *rec, long long p0, long long nlines, int nchunk,
+                                                       int nzp, float *img) {
   __shared__ float acc[2 * kZPart * kLanes];
+  if (!*cyl) return;
   const long long blk = (long long)blockIdx.x;
   const long long per_line = (long long)nchunk * nzp;
   if (blk / per_line >= nlines) return;
@@ -517,9 +523,10 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const unsigned
 // kPerEvent).  Each wavefront reads the keys of 64 events at a time and
 // projects the marked ones one after the other (a whole wavefront per
 // event, as the plain back projection); the grid strides over the list.
-__global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const float *v, const int16_t *ev, const int *key,
-                                                   long long n, float *img) {
+__global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const int *cyl, const float *v, const int16_t *ev,
+                                                   const int *key, long long n, float *img) {
   __shared__ Stage1 st[4];
+  if (!*cyl) return;
   const int lane = threadIdx.x % kLanes, wv = threadIdx.x / kLanes;
   const long long nw = (long long)gridDim.x * 4;
   for (long long b0 = ((long long)blockIdx.x * 4 + wv) * kLanes; b0 < n; b0 += nw * kLanes) {
@@ -544,40 +551,42 @@ __global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const float *v, co
   }
 }
 
+// The scanner is cylindrical when crystal c of ring r sits at (x_c, y_c, z_r):
+// the same transaxial position in every ring and one z per ring, with z_r
+// increasing in r.  One block checks every crystal and writes flag[0] = 1
+// (cylindrical) or 0; the kernels of the two paths read the flag, so the
+// decision never waits for the host.
+__global__ __launch_bounds__(256) void k_cylindrical(GeomDev g, int *flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int b = 0;
+  const float *d = g.det;
+  for (int i = threadIdx.x; i < g.n_det; i += 256) {
+    const int r = i / g.n_cry, c = i - r * g.n_cry;
+    const float *p = d + 3 * (long long)i;
+    if (p[0] != d[3 * c] || p[1] != d[3 * c + 1] || p[2] != d[3 * (long long)g.n_cry * r + 2]) b = 1;
+    if (c == 0 && r > 0 && !(p[2] > d[3 * (long long)g.n_cry * (r - 1) + 2])) b = 1;
+  }
+  if (b) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) flag[0] = bad ? 0 : 1;
+}
+
 }  // namespace
 
 namespace lmk {
 
-// The scanner is cylindrical when crystal c of ring r sits at (x_c, y_c, z_r):
-// the same transaxial position in every ring and one z per ring, with z_r
-// increasing in r.
-static int cylindrical(const GeomDev &g, hipStream_t st, bool &yes) {
-  std::vector<float> d((size_t)g.n_det * 3);
-  LM_TRY_HIP(hipMemcpyAsync(d.data(), g.det, d.size() * sizeof(float), hipMemcpyDeviceToHost, st));
-  LM_TRY_HIP(hipStreamSynchronize(st));
-  yes = true;
-  for (int r = 0; r < g.n_ring && yes; ++r)
-    for (int c = 0; c < g.n_cry; ++c) {
-      const float *p = &d[3 * ((size_t)g.n_cry * r + c)];
-      if (p[0] != d[3 * c] || p[1] != d[3 * c + 1] || p[2] != d[3 * (size_t)g.n_cry * r + 2]) {
-        yes = false;
-        break;
-      }
-    }
-  for (int r = 1; r < g.n_ring && yes; ++r)
-    if (!(d[3 * (size_t)g.n_cry * r + 2] > d[3 * (size_t)g.n_cry * (r - 1) + 2])) yes = false;
+bool lines_possible(const GeomDev &g) { return g.n_ring >= 2 && g.n_cry >= 2; }
+
+int launch_cylindrical(const GeomDev &g, int *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_cylindrical, dim3(1), dim3(256), 0, st, g, flag);
+  LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
 
-// Sensitivity by transaxial line; returns LM_OK with `done` false when the
-// scanner or image does not qualify (the caller then uses the per-LOR
-// kernel).
-int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done) {
-  done = false;
-  if (g.n_ring < 2 || g.n_cry < 2) return LM_OK;
-  bool cyl = false;
-  if (int rc = cylindrical(g, st, cyl)) return rc;
-  if (!cyl) return LM_OK;
+// Sensitivity by transaxial line; its kernels do nothing unless *cyl is set.
+int launch_sens_lines(const GeomDev &g, const int *cyl, float *img, hipStream_t st) {
   const int na_max = std::max(g.n[0], g.n[1]);
   const int nchunk = (na_max + kLanes - 1) / kLanes;
   const int nzp = (g.n[2] + kZPart - 1) / kZPart;
@@ -586,17 +595,16 @@ int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done) 
   const long long per = std::max<long long>(1, (1LL << 24) / ((long long)nchunk * nzp));
   for (long long p0 = 0; p0 < nlines; p0 += per) {
     const long long m = std::min(per, nlines - p0);
-    hipLaunchKernelGGL(k_sens_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, p0, m, nchunk,
+    hipLaunchKernelGGL(k_sens_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, cyl, p0, m, nchunk,
                        nzp, img);
     LM_TRY_HIP(hipGetLastError());
   }
   const long long npz = (long long)g.n_cry * (g.n_cry + 1) / 2;  // c1 <= c2
   for (long long p0 = 0; p0 < npz; p0 += (1LL << 24)) {
     const long long m = std::min(1LL << 24, npz - p0);
-    hipLaunchKernelGGL(k_sens_zdom, dim3((unsigned)m), dim3(kLanes), 0, st, g, p0, m, img);
+    hipLaunchKernelGGL(k_sens_zdom, dim3((unsigned)m), dim3(kLanes), 0, st, g, cyl, p0, m, img);
     LM_TRY_HIP(hipGetLastError());
   }
-  done = true;
   return LM_OK;
 }
 
@@ -606,15 +614,12 @@ int launch_sens_lines(const GeomDev &g, float *img, hipStream_t st, bool &done) 
 // a few tens of events do on the per-event path).
 constexpr long long kMinEventsPerLine = 64;
 
-int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st,
-                      bool &done) {
-  done = false;
+int launch_back_lines(const GeomDev &g, const int *cyl, const float *v, const int16_t *ev, long long n, float *img,
+                      hipStream_t st, bool &queued) {
+  queued = false;
   const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
-  if (g.n_ring < 2 || g.n_cry < 2 || g.n_ring > 4096 || g.n_tof > 255) return LM_OK;
+  if (!lines_possible(g) || g.n_ring > 4096 || g.n_tof > 255) return LM_OK;
   if (n < kMinEventsPerLine * nlines || n >= (1LL << 31) || nlines >= (1LL << 31)) return LM_OK;
-  bool cyl = false;
-  if (int rc = cylindrical(g, st, cyl)) return rc;
-  if (!cyl) return LM_OK;
   int *key = nullptr;
   unsigned *rank = nullptr, *cnt = nullptr, *off = nullptr;
   LineRec *rec = nullptr;
@@ -639,15 +644,15 @@ int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long 
   if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, nlines * sizeof(unsigned), st);
   const unsigned grid = (unsigned)((n + 255) / 256);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_keys, dim3(grid), dim3(256), 0, st, g, ev, v, n, key, rank, cnt);
+    hipLaunchKernelGGL(k_line_keys, dim3(grid), dim3(256), 0, st, g, cyl, ev, v, n, key, rank, cnt);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, cnt, nlines, off);
+    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, cyl, cnt, nlines, off);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_place, dim3(grid), dim3(256), 0, st, g, ev, v, n, key, rank, off, rec);
+    hipLaunchKernelGGL(k_line_place, dim3(grid), dim3(256), 0, st, g, cyl, ev, v, n, key, rank, off, rec);
     e = hipGetLastError();
   }
   const int na_max = std::max(g.n[0], g.n[1]);
@@ -656,19 +661,19 @@ int launch_back_lines(const GeomDev &g, const float *v, const int16_t *ev, long 
   const long long per = std::max<long long>(1, (1LL << 24) / ((long long)nchunk * nzp));
   for (long long p0 = 0; e == hipSuccess && p0 < nlines; p0 += per) {
     const long long m = std::min(per, nlines - p0);
-    hipLaunchKernelGGL(k_back_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, off, rec, p0, m,
-                       nchunk, nzp, img);
+    hipLaunchKernelGGL(k_back_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, cyl, off, rec, p0,
+                       m, nchunk, nzp, img);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
     // 4096 blocks of 4 wavefronts stride over the list
     const long long nb = std::min<long long>(4096, (n + 4 * kLanes - 1) / (4 * kLanes));
-    hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)nb), dim3(256), 0, st, g, v, ev, key, n, img);
+    hipLaunchKernelGGL(k_back_zdom, dim3((unsigned)nb), dim3(256), 0, st, g, cyl, v, ev, key, n, img);
     e = hipGetLastError();
   }
   release();
   LM_TRY_HIP(e);
-  done = true;
+  queued = true;
   return LM_OK;
 }
 

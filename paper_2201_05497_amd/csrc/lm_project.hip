@@ -74,54 +74,59 @@ struct Stage {
 };
 
 // Back projection: one event per wavefront, the scatter of every 64 planes
-// interleaved over corners.
+// interleaved over corners; the grid strides over the list.  With `skip`
+// set the kernel does nothing when *skip is non-zero (the list went to the
+// transaxial-line path instead).
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const float *__restrict__ v, Src src, long long n,
-                                                 float *img) {
+__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, const int *skip, const float *__restrict__ v, Src src,
+                                                 long long n, float *img) {
   __shared__ Stage st;
+  if (skip && *skip) return;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  const long long e = (long long)blockIdx.x * (kBlock / 64) + wv;
-  if (e >= n) return;
-  const float ve = v[e];
-  if (ve == 0.0f) return;
-  int id1, id2, k;
-  if (!src.get(g, e, id1, id2, k)) return;
-  const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
-  const float c = r.L * ve;
-  const int off = brick_offset(g.lay, r);
-  for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
-    const int j = j0 + lane;
-    Sample s = sample_at(g, r, j, g.tof_on);
-    const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
-    scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
+  const long long stride = (long long)gridDim.x * (kBlock / 64);
+  for (long long e = (long long)blockIdx.x * (kBlock / 64) + wv; e < n; e += stride) {
+    const float ve = v[e];
+    if (ve == 0.0f) continue;
+    int id1, id2, k;
+    if (!src.get(g, e, id1, id2, k)) continue;
+    const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
+    const float c = r.L * ve;
+    const int off = brick_offset(g.lay, r);
+    for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
+      const int j = j0 + lane;
+      Sample s = sample_at(g, r, j, g.tof_on);
+      const float cs = (j >= 0 && j < r.nplanes) ? c * s.w : 0.0f;
+      scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
+    }
   }
 }
 
 // Sensitivity: every unordered pair (id1 < id2) of crystals, weight summed
-// over all TOF bins, one pair per wavefront.  Pair index p in [p0, p0 + np)
-// of the row-major upper triangle.
-__global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, long long p0, long long np, float *img) {
+// over all TOF bins, one pair per wavefront, the grid striding over the
+// pairs; nothing when *skip is non-zero (the pairs went to the line path).
+__global__ __launch_bounds__(kBlock) void k_sens(GeomDev g, const int *skip, long long npairs, float *img) {
   __shared__ Stage st;
+  if (skip && *skip) return;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  const long long q = (long long)blockIdx.x * (kBlock / 64) + wv;
-  if (q >= np) return;
-  const long long p = p0 + q;
   const long long nd = g.n_det;
-  // row i holds pairs (i, i+1..nd-1); first index of row i is i*nd - i(i+1)/2
-  const double b = 2.0 * nd - 1.0;
-  long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
-  auto first = [&](long long r) { return r * nd - r * (r + 1) / 2; };
-  if (i < 0) i = 0;
-  while (i > 0 && first(i) > p) --i;
-  while (i + 1 < nd && first(i + 1) <= p) ++i;
-  const long long jdx = i + 1 + (p - first(i));
-  const Ray r = setup_ray(g, (int)i, (int)jdx, 0, W_SUM, 1 << 20);
-  const int off = brick_offset(g.lay, r);
-  for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
-    const int j = j0 + lane;
-    Sample s = sample_at(g, r, j, g.tof_on);
-    const float cs = (j >= 0 && j < r.nplanes) ? r.L * s.w : 0.0f;
-    scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
+  const long long stride = (long long)gridDim.x * (kBlock / 64);
+  for (long long p = (long long)blockIdx.x * (kBlock / 64) + wv; p < npairs; p += stride) {
+    // row i holds pairs (i, i+1..nd-1); first index of row i is i*nd - i(i+1)/2
+    const double b = 2.0 * nd - 1.0;
+    long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+    auto first = [&](long long r) { return r * nd - r * (r + 1) / 2; };
+    if (i < 0) i = 0;
+    while (i > 0 && first(i) > p) --i;
+    while (i + 1 < nd && first(i + 1) <= p) ++i;
+    const long long jdx = i + 1 + (p - first(i));
+    const Ray r = setup_ray(g, (int)i, (int)jdx, 0, W_SUM, 1 << 20);
+    const int off = brick_offset(g.lay, r);
+    for (int j0 = -off; j0 < r.nplanes; j0 += 64) {
+      const int j = j0 + lane;
+      Sample s = sample_at(g, r, j, g.tof_on);
+      const float cs = (j >= 0 && j < r.nplanes) ? r.L * s.w : 0.0f;
+      scatter_interleaved(g, img, r, s, cs, lane, st.idx[wv], st.val[wv]);
+    }
   }
 }
 
@@ -286,45 +291,78 @@ static int fwd_impl(const GeomDev &g, const float *x, Src src, long long n, floa
   return LM_OK;
 }
 
+// Grid of the grid-stride scattering kernels: enough wavefronts to fill the
+// chip many times over, few enough that a launch whose work went to another
+// path costs next to nothing.
+constexpr long long kStrideBlocks = 1LL << 16;
+
 template <class Src>
-static int back_impl(const GeomDev &g, const float *v, Src src, long long n, float *img, hipStream_t st) {
+static int back_impl(const GeomDev &g, const int *skip, const float *v, Src src, long long n, float *img,
+                     hipStream_t st) {
   if (n == 0) return LM_OK;
-  for (long long o = 0; o < n; o += chunk_items(64)) {
-    const long long m = std::min(chunk_items(64), n - o);
-    hipLaunchKernelGGL((k_back<Src>), dim3(blocks_for(m, 64)), dim3(kBlock), 0, st, g, v + o, src.offset(o), m, img);
-    LM_TRY_HIP(hipGetLastError());
-  }
+  const long long nb = std::min<long long>(kStrideBlocks, blocks_for(n, 64));
+  hipLaunchKernelGGL((k_back<Src>), dim3((unsigned)nb), dim3(kBlock), 0, st, g, skip, v, src, n, img);
+  LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
+
+// A device flag (one int), allocated and freed stream-ordered.
+struct DevFlag {
+  int *p = nullptr;
+  hipStream_t st = nullptr;
+  int alloc(hipStream_t s) {
+    st = s;
+    const hipError_t e = hipMallocAsync((void **)&p, sizeof(int), s);
+    if (e != hipSuccess) {
+      p = nullptr;
+      lmh::set_error("flag temporary: %s", hipGetErrorString(e));
+      return LM_ENOMEM;
+    }
+    return LM_OK;
+  }
+  ~DevFlag() {
+    if (p) (void)hipFreeAsync(p, st);  // a release error has no caller to go to
+  }
+};
 
 int launch_fwd(const GeomDev &g, const float *x, const int16_t *ev, long long n, float *out, hipStream_t st) {
   return fwd_impl(g, x, CallerEvents{ev}, n, out, st);
 }
 int launch_back(const GeomDev &g, const float *v, const int16_t *ev, long long n, float *img, hipStream_t st) {
-  bool done = false;
-  if (int rc = launch_back_lines(g, v, ev, n, img, st, done)) return rc;
-  if (done) return LM_OK;
-  return back_impl(g, v, CallerEvents{ev}, n, img, st);
+  if (n == 0) return LM_OK;
+  DevFlag cyl;
+  bool queued = false;
+  if (lines_possible(g)) {
+    if (int rc = cyl.alloc(st)) return rc;
+    if (int rc = launch_cylindrical(g, cyl.p, st)) return rc;
+    if (int rc = launch_back_lines(g, cyl.p, v, ev, n, img, st, queued)) return rc;
+  }
+  // the per-event kernel takes the list when the line path was not queued,
+  // or was queued on a scanner that is not cylindrical
+  return back_impl(g, queued ? cyl.p : nullptr, v, CallerEvents{ev}, n, img, st);
 }
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out, hipStream_t st) {
   return fwd_impl(g, x, PlanEvents{rec}, n, out, st);
 }
 int launch_back_rec(const GeomDev &g, const float *v, const int4 *rec, long long n, float *img, hipStream_t st) {
-  return back_impl(g, v, PlanEvents{rec}, n, img, st);
+  return back_impl(g, nullptr, v, PlanEvents{rec}, n, img, st);
 }
 
 int launch_sens(const GeomDev &g, float *img, hipStream_t st) {
-  bool done = false;
-  if (int rc = launch_sens_lines(g, img, st, done)) return rc;
-  if (done) return LM_OK;
   const long long nd = g.n_det;
   const long long npairs = nd * (nd - 1) / 2;
-  const long long chunk = chunk_items(64);
-  for (long long p0 = 0; p0 < npairs; p0 += chunk) {
-    const long long np = std::min(chunk, npairs - p0);
-    hipLaunchKernelGGL(k_sens, dim3(blocks_for(np, 64)), dim3(kBlock), 0, st, g, p0, np, img);
+  const long long nb = std::min<long long>(kStrideBlocks, blocks_for(npairs, 64));
+  if (!lines_possible(g)) {
+    hipLaunchKernelGGL(k_sens, dim3((unsigned)nb), dim3(kBlock), 0, st, g, nullptr, npairs, img);
     LM_TRY_HIP(hipGetLastError());
+    return LM_OK;
   }
+  DevFlag cyl;
+  if (int rc = cyl.alloc(st)) return rc;
+  if (int rc = launch_cylindrical(g, cyl.p, st)) return rc;
+  if (int rc = launch_sens_lines(g, cyl.p, img, st)) return rc;
+  hipLaunchKernelGGL(k_sens, dim3((unsigned)nb), dim3(kBlock), 0, st, g, cyl.p, npairs, img);
+  LM_TRY_HIP(hipGetLastError());
   return LM_OK;
 }
 
@@ -353,31 +391,6 @@ int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const 
 
 }  // namespace lmk
 
-// The plain projector calls run on a bricked copy of the caller's row-major
-// image (the layout of the plans, 4x4x4 voxels per brick): gathers and the
-// interleaved scatter then touch few cache lines per instruction.  The copy
-// is a stream-ordered temporary freed (stream-ordered) when the call
-// returns; its padding voxels are never read or written, since every
-// corner is checked against the image size.
-struct BrickImage {
-  float *p = nullptr;
-  hipStream_t st = nullptr;
-  int alloc(GeomDev &g, hipStream_t s) {
-    g.lay = lmh::brick_layout(g.n);
-    st = s;
-    const hipError_t e = hipMallocAsync((void **)&p, (size_t)layout_size(g.lay) * sizeof(float), s);
-    if (e != hipSuccess) {
-      p = nullptr;
-      lmh::set_error("image temporary: %s", hipGetErrorString(e));
-      return LM_ENOMEM;
-    }
-    return LM_OK;
-  }
-  ~BrickImage() {
-    if (p) (void)hipFreeAsync(p, st);  // a release error has no caller to go to
-  }
-};
-
 // --------------------------------------------------------------------------
 // C ABI
 
@@ -391,7 +404,7 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
   LM_REQUIRE(n == 0 || (x && ev && out), LM_EINVAL, "NULL array");
   if (n == 0) return LM_OK;
   hipStream_t st = lmh::as_stream(stream);
-  BrickImage b;
+  lmh::BrickImage b;
   if (int rc = b.alloc(g, st)) return rc;
   if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, x, b.p, st)) return rc;
   return launch_fwd(g, b.p, ev, n, out, st);
@@ -405,7 +418,7 @@ int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, floa
   LM_REQUIRE(n == 0 || (v && ev && img), LM_EINVAL, "NULL array");
   if (n == 0) return LM_OK;
   hipStream_t st = lmh::as_stream(stream);
-  BrickImage b;
+  lmh::BrickImage b;
   if (int rc = b.alloc(g, st)) return rc;
   if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, img, b.p, st)) return rc;
   if (int rc = launch_back(g, v, ev, n, b.p, st)) return rc;
@@ -418,7 +431,7 @@ int lm_sens(const lm_geom *G, float *img, void *stream) {
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(img != nullptr, LM_EINVAL, "NULL image");
   hipStream_t st = lmh::as_stream(stream);
-  BrickImage b;
+  lmh::BrickImage b;
   if (int rc = b.alloc(g, st)) return rc;
   if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, img, b.p, st)) return rc;
   if (int rc = launch_sens(g, b.p, st)) return rc;
