@@ -99,10 +99,10 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
  * v = 0 contribute nothing.  On a cylindrical scanner (crystal c of ring r
  * at (x_c, y_c, z_r), z increasing with r) a list of at least 64 events per
  * transaxial crystal pair is back projected by transaxial line after a
- * counting sort on the device: 16 more bytes per event of stream-ordered
- * temporary memory (without room for it the per-event path runs), and one
- * host synchronisation of `stream` (the crystal table is read back to
- * check the scanner's shape). */
+ * counting sort on the device; the list then needs 16 more bytes per event
+ * of stream-ordered temporary memory (without room for it the per-event
+ * path runs).  Whether the scanner is cylindrical is decided by a kernel
+ * that reads the crystal table: the call never synchronises the stream. */
 int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img,
             void *stream);
 
@@ -110,8 +110,8 @@ int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, floa
  * TOF bin (the back projection of a sinogram of ones that Algorithm 2's
  * initialisation and the step sizes T need; Section 2, after Eq.
  * lm_stepsizes).  Accumulates into g; the caller zeroes it.  On a
- * cylindrical 3D scanner (as for lm_back) the pairs are taken by transaxial
- * line, which synchronises `stream` once to check the scanner's shape. */
+ * cylindrical 3D scanner (as for lm_back, decided on the device) the pairs
+ * are taken by transaxial line.  Asynchronous. */
 int lm_sens(const lm_geom *G, float *g, void *stream);
 
 /* Synchronous: count events whose crystal, ring or TOF index is out of
@@ -130,16 +130,39 @@ int tv_grad(const int32_t n[3], const float *x, float *gx, void *stream);
  * float[3][nz][ny][nx]. */
 int tv_div(const int32_t n[3], const float *w, float *out, void *stream);
 
+/* ---------------------------------------------------------------- cost */
+
+/* Synchronous.  The objective of Eq. (1) in listmode form, for monitoring
+ * (the relative cost c_rel(x) = (c(x) - c(x*)) / (c(x0) - c(x*)) of
+ * Section 3, Numerical Experiments):
+ *   c(x) = <g, x> - sum_e log((P^LM x)_e + s_e) + beta ||K x||_{2,1},
+ * where g = P^T 1 (sum_i (Px)_i over all bins is <g, x>) and each event
+ * gives the log term of its bin once; the constant sum of s over all bins
+ * is left out.  K is the forward-difference gradient of tv_grad.  x, g:
+ * row-major float images; ev: int16[n][5]; s: float[n] (> 0 keeps the
+ * logarithms finite).  Outputs (host, either may be NULL but not both):
+ * *cost, and terms[3] = {<g, x>, sum_e log((P^LM x)_e + s_e), ||K x||_{2,1}}.
+ * The projections are float32 (lm_fwd); the sums are accumulated in
+ * double.  Temporaries (4 B per event, a bricked copy of x) are allocated
+ * stream-ordered. */
+int lm_cost(const lm_geom *G, const float *x, const int16_t *ev, const float *s, int64_t n, const float *g,
+            double beta, double *cost, double *terms, void *stream);
+
 /* ---------------------------------------------------------------- LM-SPDHG */
 
 typedef struct lm_plan lm_plan;
 
 /* Device bytes a plan for n_ev events and n_sub subsets will allocate,
  * including the temporary memory of lm_plan_create; host output *bytes.
- * Used to admit reconstructions against an HBM budget.  The optional parts
- * (lm_plan_set_prior_image, lm_plan_set_event_factors,
- * lm_plan_set_resolution) allocate more, as each of them states. */
+ * Used to admit reconstructions against an HBM budget.  lm_plan_bytes
+ * counts the base plan; lm_plan_bytes_ex adds the optional parts named in
+ * `parts` (an OR of the LM_PART_* flags): the directional TV prior
+ * (lm_plan_set_prior_image), per-event factors (lm_plan_set_event_factors)
+ * and the resolution model (lm_plan_set_resolution).  LM_EINVAL for an
+ * unknown flag. */
+enum { LM_PART_DTV = 1, LM_PART_FACTORS = 2, LM_PART_RESOLUTION = 4 };
 int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes);
+int lm_plan_bytes_ex(const lm_geom *G, int64_t n_ev, int32_t n_sub, int32_t parts, size_t *bytes);
 
 /* Synchronous.  Builds a plan: copies and validates the events (LM_ERANGE
  * on any out-of-range index, nothing allocated), computes the event counts
@@ -194,8 +217,10 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq_host, int32_t n_upda
  * lm_plan_get_lists still returns the integer counts.  P^LM 1 as read back
  * stays the geometric one.  m: float[n], device, caller event order.
  * Synchronous.  Call once, after lm_plan_create and before lm_spdhg_init or
- * lm_plan_set_state (LM_ESTATE otherwise).  LM_ERANGE if a factor is not
- * positive and finite (nothing changed). */
+ * lm_plan_set_state (LM_ESTATE otherwise).  LM_ESTATE as well when the plan
+ * computed g itself (lm_plan_create with g = NULL): the sensitivity of P'
+ * sums m over every LOR, which the event list cannot give.  LM_ERANGE if a
+ * factor is not positive and finite (nothing changed). */
 int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream);
 
 /* Image-space resolution model (Section 1: P includes limited spatial
@@ -208,7 +233,9 @@ int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream);
  * projections and blurs its back projection before the z step: four more
  * images of plan memory and two passes per blurred axis.  P^LM 1 and S_e are
  * recomputed for G B; the g given to lm_plan_create must be the sensitivity
- * of the whole operator.  Synchronous.  Before lm_spdhg_init or
+ * of the whole operator.  When the plan computed g = G^T 1 itself (g = NULL
+ * at creation) it replaces it by B G^T 1, the sensitivity of G B, and
+ * recomputes T (one more image of plan memory).  Synchronous.  Before lm_spdhg_init or
  * lm_plan_set_state (LM_ESTATE otherwise); LM_EINVAL for a negative FWHM or
  * one beyond 16 taps of radius. */
 int lm_plan_set_resolution(lm_plan *p, const double fwhm_vox[3], void *stream);

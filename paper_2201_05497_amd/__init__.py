@@ -12,7 +12,7 @@ Eq. (1) with a time-of-flight Joseph projector and a TV prior.
 from __future__ import annotations
 
 import ctypes
-from typing import Optional, Sequence
+from typing import Optional
 
 import numpy as np
 import torch
@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LMError
 
 __all__ = ["Geometry", "lm_fwd", "lm_back", "lm_sens", "lm_validate_events", "tv_grad", "tv_div",
-           "lm_plan_bytes", "Plan", "lm_emtv", "LMError", "exact_grad_norm"]
+           "lm_cost", "lm_plan_bytes", "Plan", "lm_emtv", "LMError", "PART_DTV", "PART_FACTORS", "PART_RESOLUTION"]
 
 _L = _lib.load()
 
@@ -45,12 +45,6 @@ def _need(t: torch.Tensor, dtype, name: str, device: torch.device, numel: Option
         raise ValueError(f"{name} must be contiguous")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
-
-
-def exact_grad_norm(n: Sequence[int]) -> float:
-    """Largest singular value of the forward-difference operator on an image
-    of size n (the value the library uses when knorm <= 0)."""
-    return float(np.sqrt(sum(4.0 * np.sin(np.pi * (N - 1) / (2.0 * N)) ** 2 for N in n)))
 
 
 class Geometry:
@@ -210,11 +204,32 @@ def lm_emtv(geom: Geometry, ev: torch.Tensor, s: torch.Tensor, g: torch.Tensor, 
     return x
 
 
-def lm_plan_bytes(geom: Geometry, n_events: int, n_subsets: int) -> int:
-    """Device bytes a plan allocates (used for admission against a budget)."""
+def lm_cost(geom: Geometry, x: torch.Tensor, ev: torch.Tensor, s: torch.Tensor, g: torch.Tensor,
+            beta: float) -> tuple:
+    """(c(x), (<g, x>, sum_e log((P^LM x)_e + s_e), ||K x||_{2,1})): the
+    listmode form of the objective of Eq. (1) without the constant sum of s
+    over all bins (synchronous)."""
+    n = _ev_check(geom, ev)
+    _need(x, torch.float32, "x", geom.device, geom.nvox)
+    _need(g, torch.float32, "g", geom.device, geom.nvox)
+    _need(s, torch.float32, "s", geom.device, n)
+    c = ctypes.c_double(0.0)
+    t = (ctypes.c_double * 3)()
+    _lib.check(_L.lm_cost(ctypes.byref(geom._c), x.data_ptr(), ev.data_ptr(), s.data_ptr(), n, g.data_ptr(),
+                          float(beta), ctypes.byref(c), t, _stream(geom.device)), "lm_cost")
+    return float(c.value), (float(t[0]), float(t[1]), float(t[2]))
+
+
+# optional parts of a plan, for lm_plan_bytes(parts=...)
+PART_DTV, PART_FACTORS, PART_RESOLUTION = 1, 2, 4
+
+
+def lm_plan_bytes(geom: Geometry, n_events: int, n_subsets: int, parts: int = 0) -> int:
+    """Device bytes a plan allocates (used for admission against a budget),
+    with the optional parts in `parts` (an OR of PART_*)."""
     b = ctypes.c_size_t(0)
-    _lib.check(_L.lm_plan_bytes(ctypes.byref(geom._c), int(n_events), int(n_subsets), ctypes.byref(b)),
-               "lm_plan_bytes")
+    _lib.check(_L.lm_plan_bytes_ex(ctypes.byref(geom._c), int(n_events), int(n_subsets), int(parts),
+                                   ctypes.byref(b)), "lm_plan_bytes_ex")
     return int(b.value)
 
 

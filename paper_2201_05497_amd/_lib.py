@@ -36,7 +36,10 @@ SIGNATURES = {
     "lm_validate_events": (ctypes.c_int, [_GP, _VP, _I64, ctypes.POINTER(ctypes.c_int64), _VP]),
     "tv_grad": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), _VP, _VP, _VP]),
     "tv_div": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), _VP, _VP, _VP]),
+    "lm_cost": (ctypes.c_int, [_GP, _VP, _VP, _VP, _I64, _VP, _D, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), _VP]),
     "lm_plan_bytes": (ctypes.c_int, [_GP, _I64, _I32, ctypes.POINTER(ctypes.c_size_t)]),
+    "lm_plan_bytes_ex": (ctypes.c_int, [_GP, _I64, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)]),
     "lm_plan_create": (ctypes.c_int, [_GP, _VP, _VP, _I64, _I32, _VP, _D, _D, _D, _D, _VP,
                                       ctypes.POINTER(_VP)]),
     "lm_spdhg_init": (ctypes.c_int, [_VP, _VP, _VP]),

@@ -89,6 +89,10 @@ struct lm_plan {
   // B dz after them, and two temporaries of the separable passes
   lmk::Blur blur{};
   float *xb = nullptr, *dzb = nullptr, *bt1 = nullptr, *bt2 = nullptr;
+  // the plan computed g = G^T 1 itself (lm_plan_create with g = NULL); g0
+  // keeps that image when a resolution model later replaces g by B g0
+  bool g_internal = false;
+  float *g0 = nullptr;
   std::vector<void *> allocs;
   bool initialized = false;
   long long u = 0;
@@ -109,6 +113,9 @@ inline unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBl
 
 constexpr unsigned long long kEmpty = ~0ULL;
 
+// The 64-bit finaliser ("fmix64") of Austin Appleby's public-domain
+// MurmurHash3, with its published constants: every input bit affects every
+// output bit, so nearby bin keys spread over the table.
 __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
   x ^= x >> 33;
   x *= 0xff51afd7ed558ccdULL;
@@ -349,13 +356,26 @@ int timed(lm_plan *p, int cls, hipStream_t st, F &&launch) {
 extern "C" {
 
 int lm_plan_bytes(const lm_geom *G, int64_t n_ev, int32_t n_sub, size_t *bytes) {
+  return lm_plan_bytes_ex(G, n_ev, n_sub, 0, bytes);
+}
+
+int lm_plan_bytes_ex(const lm_geom *G, int64_t n_ev, int32_t n_sub, int32_t parts, size_t *bytes) {
   lmh::clear_error();
   lmk::GeomDev g;
   if (int rc = lmh::make_geom(G, &g)) return rc;
   LM_REQUIRE(n_ev >= 0 && n_sub >= 1 && bytes, LM_EINVAL, "bad arguments");
+  LM_REQUIRE((parts & ~(LM_PART_DTV | LM_PART_FACTORS | LM_PART_RESOLUTION)) == 0, LM_EINVAL,
+             "unknown plan parts 0x%x", (unsigned)parts);
   const int ncomp = G->n[2] > 1 ? 3 : 2;
-  const Sizes s = plan_sizes(n_ev, n_sub, lmh::nvox_of(G->n), lmk::layout_size(lmh::brick_layout(G->n)), ncomp);
-  *bytes = s.persistent + s.temporary;
+  const long long E = lmk::layout_size(lmh::brick_layout(G->n));
+  const Sizes s = plan_sizes(n_ev, n_sub, lmh::nvox_of(G->n), E, ncomp);
+  size_t extra = 0;
+  // allocations of the optional parts (each with the one-element minimum of
+  // the plan's allocator)
+  if (parts & LM_PART_DTV) extra += 2 * (size_t)E * ncomp * sizeof(float);
+  if (parts & LM_PART_FACTORS) extra += (size_t)std::max<int64_t>(n_ev, 1) * sizeof(float);
+  if (parts & LM_PART_RESOLUTION) extra += 5 * (size_t)E * sizeof(float);  // B x, B dz, 2 temporaries, g0
+  *bytes = s.persistent + s.temporary + extra;
   return LM_OK;
 }
 
@@ -483,6 +503,7 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   } else {
     step(hipMemsetAsync(p->gimg, 0, E * sizeof(float), st), "zero g");
     if (rc == LM_OK) rc = lmk::launch_sens(p->g, p->gimg, st);  // bricked geometry
+    p->g_internal = true;
   }
   hipLaunchKernelGGL(k_step_T, dim3(grid_for(E)), dim3(kBlock), 0, st, p->gimg, p->T, (float)(rho / (2.0 * gamma)),
                      (float)p->knorm, E);
@@ -607,6 +628,9 @@ int lm_plan_set_event_factors(lm_plan *p, const float *m, void *stream) {
   LM_REQUIRE(p && m, LM_EINVAL, "NULL plan or factors");
   LM_REQUIRE(!p->initialized, LM_ESTATE, "event factors must be set before lm_spdhg_init");
   LM_REQUIRE(!p->mfac, LM_ESTATE, "event factors are already set");
+  LM_REQUIRE(!p->g_internal, LM_ESTATE,
+             "the plan computed g = P^T 1 itself; with factors g must be the sensitivity of diag(m) P over all "
+             "LORs, which the event list cannot give: pass it to lm_plan_create");
   const long long N = p->n;
   if (N == 0) return LM_OK;
   hipStream_t st = lmh::as_stream(stream);
@@ -660,6 +684,22 @@ int lm_plan_set_resolution(lm_plan *p, const double fwhm_vox[3], void *stream) {
     hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(p->gamma * p->rho), N);
     LM_TRY_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, ones, 0.0f, E);
+    LM_TRY_HIP(hipGetLastError());
+  }
+  if (p->g_internal) {
+    // the plan's own g = G^T 1 becomes the sensitivity of G B, B G^T 1 (B is
+    // symmetric), and T follows it
+    if (!p->g0) {
+      if (int rc = dalloc(p, &p->g0, (size_t)E)) return rc;
+      LM_TRY_HIP(hipMemcpyAsync(p->g0, p->gimg, E * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    if (b.on) {
+      if (int rc = lmk::launch_blur(p->G.n, p->lay, E, b, p->g0, p->gimg, p->bt1, p->bt2, st)) return rc;
+    } else {
+      LM_TRY_HIP(hipMemcpyAsync(p->gimg, p->g0, E * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_step_T, dim3(grid_for(E)), dim3(kBlock), 0, st, p->gimg, p->T,
+                       (float)(p->rho / (2.0 * p->gamma)), (float)p->knorm, E);
     LM_TRY_HIP(hipGetLastError());
   }
   LM_TRY_HIP(hipStreamSynchronize(st));

@@ -51,6 +51,27 @@ def test_plan_bytes_host_only(lib):
     assert b.value > small > 0
 
 
+def test_plan_bytes_optional_parts(lib):
+    """lm_plan_bytes_ex adds the memory of each optional part to the base
+    plan (lm_plan_bytes) and rejects unknown part flags."""
+    L = lib.load()
+    g = _geom(lib, n=(20, 20, 8))
+    b = ctypes.c_size_t(0)
+    assert L.lm_plan_bytes(ctypes.byref(g), 5000, 4, ctypes.byref(b)) == 0
+    base = b.value
+    assert L.lm_plan_bytes_ex(ctypes.byref(g), 5000, 4, 0, ctypes.byref(b)) == 0
+    assert b.value == base
+    ne = 20 * 20 * 8  # whole 4x4x4 bricks: no padding at this size
+    sizes = {}
+    for part, want in ((1, 2 * 3 * ne * 4), (2, 5000 * 4), (4, 5 * ne * 4)):
+        assert L.lm_plan_bytes_ex(ctypes.byref(g), 5000, 4, part, ctypes.byref(b)) == 0
+        sizes[part] = b.value - base
+        assert sizes[part] == want, (part, sizes[part], want)
+    assert L.lm_plan_bytes_ex(ctypes.byref(g), 5000, 4, 7, ctypes.byref(b)) == 0
+    assert b.value == base + sum(sizes.values())
+    assert L.lm_plan_bytes_ex(ctypes.byref(g), 5000, 4, 8, ctypes.byref(b)) == lib.LM_EINVAL
+
+
 @pytest.mark.parametrize("field,value", [("n_tof", 4), ("n_tof", 0), ("n_cry", 0)])
 def test_invalid_geometry_rejected(lib, field, value):
     L = lib.load()
@@ -99,3 +120,4 @@ def test_new_entry_points_check_arguments_first(lib):
     assert L.lm_plan_set_prior_image(None, P_, 0.1, None) == lib.LM_EINVAL
     assert L.lm_plan_set_event_factors(None, P_, None) == lib.LM_EINVAL
     assert L.lm_plan_set_resolution(None, f3, None) == lib.LM_EINVAL
+
