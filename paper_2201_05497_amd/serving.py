@@ -32,6 +32,7 @@ import numpy as np
 import torch
 
 from . import Geometry, Plan, lm_plan_bytes, lm_sens
+from .sequence import subset_sequence
 
 __all__ = ["Request", "Result", "Server", "solve", "latency_stats"]
 
@@ -61,8 +62,7 @@ class Request:
     def sequence(self) -> np.ndarray:
         if self.seq is not None:
             return np.asarray(self.seq, dtype=np.int32)
-        import lmsynth
-        return lmsynth.subset_sequence(self.seq_seed, 0, self.n_updates(), self.n_subsets)
+        return subset_sequence(self.seq_seed, 0, self.n_updates(), self.n_subsets)
 
 
 @dataclasses.dataclass

@@ -111,6 +111,19 @@ def test_product_package_never_imports_the_oracle():
             else:
                 continue
             assert not any(m == "oracle" or m.startswith("oracle.") for m in mods), (name, mods)
+            # nor the generator of the test inputs
+            assert not any(m == "lmsynth" or m.startswith("lmsynth.") for m in mods), (name, mods)
+
+
+def test_package_subset_sequence():
+    """The package draws subset choices with its own SplitMix64: the
+    published first output for seed 0, and the same choices as the input
+    generator of the tests."""
+    import lmsynth
+    from paper_2201_05497_amd import sequence
+    assert sequence.splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    for seed, u0, n in ((2001, 0, 224), (2003, 448, 28), (7, 5, 1)):
+        assert np.array_equal(sequence.subset_sequence(seed, u0, 500, n), lmsynth.subset_sequence(seed, u0, 500, n))
 
 
 def test_plan_bytes_grow_with_events_and_image():
