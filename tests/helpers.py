@@ -73,3 +73,26 @@ def smooth_image(shape, seed: int, base: float = 1.0) -> np.ndarray:
         r = rng.uniform(0.1, 0.3)
         img = np.where((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 < r * r, img * 3.0, img)
     return img.astype(np.float32)
+
+
+@functools.lru_cache(maxsize=None)
+def sens_3d_input(large: bool = False) -> np.ndarray:
+    """A dense sensitivity-like input image for the 3D workloads (the
+    200x200x96 grid, or the 300x300x96 one with `large`): the oracle's
+    non-TOF P^T 1 of a decimated scanner (every 16th crystal, every 8th
+    ring, same cylinder and axial span), rescaled to the number of crystal
+    pairs of the full one and floored at 1e-3 of its maximum so that no
+    voxel is left without a penalty on x.  It is an input of the plan like
+    any other, so both sides receive it (the full scanner's P^T 1 would take
+    the oracle hours)."""
+    import oracle
+    p = lmsynth.config_3d_large() if large else lmsynth.config_3d()
+    sc = p.scanner
+    nr = sc.n_ring // 8
+    dec = lmsynth.Scanner(sc.n_cry // 16, nr, sc.radius, sc.pitch * (sc.n_ring - 1) / (nr - 1))
+    q = lmsynth.Problem("dec", dec, p.image, p.tof, 1, 1, 0.0)
+    g = oracle.sens(oracle.Geometry.from_problem(q, tof_on=False))
+    full = sc.n_det * (sc.n_det - 1) / 2.0
+    part = dec.n_det * (dec.n_det - 1) / 2.0
+    g = g * (full / part)
+    return np.maximum(g, 1e-3 * g.max())

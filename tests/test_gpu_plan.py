@@ -12,12 +12,17 @@ import torch
 
 import lmsynth
 import oracle
-from tests.helpers import img_err, problem_2d, problem_3d, proj_err, report, smooth_image
+from tests.helpers import img_err, problem_2d, problem_3d, proj_err, report, sens_3d_input, smooth_image
 
 pytestmark = pytest.mark.gpu
 
 ITER_TOL = 1e-4
 PROJ_TOL = 1e-5
+# sup norm of the TV dual w, relative to beta: float32 rounding of the
+# state alone moves it by ~1e-3 beta in the oracle
+# (test_tv_dual_sup_norm_follows_rounding_of_the_state), while x moves by
+# ~1e-6; w is also held to ITER_TOL in relative L2
+W_SUP_TOL = 1e-2
 RHO = 0.999
 
 
@@ -33,26 +38,6 @@ def sens_2d():
     """Oracle sensitivity image of the 2D workload (all 64,620 pairs)."""
     p = problem_2d()
     return oracle.sens(oracle.Geometry.from_problem(p))
-
-
-@functools.lru_cache(maxsize=None)
-def sens_3d_input():
-    """A dense sensitivity-like input image for the 3D workload: the oracle's
-    non-TOF P^T 1 of a decimated scanner (every 16th crystal, every 8th ring,
-    same cylinder), rescaled to the number of crystal pairs of the full one.
-    It is an input of the plan like any other, so both sides receive it."""
-    p = lmsynth.config_3d()
-    sc = p.scanner
-    nr = sc.n_ring // 8
-    # same axial span: the outer rings of both scanners coincide
-    dec = lmsynth.Scanner(sc.n_cry // 16, nr, sc.radius, sc.pitch * (sc.n_ring - 1) / (nr - 1))
-    q = lmsynth.Problem("dec", dec, p.image, p.tof, 1, 1, 0.0)
-    g = oracle.sens(oracle.Geometry.from_problem(q, tof_on=False))
-    full = sc.n_det * (sc.n_det - 1) / 2.0
-    part = dec.n_det * (dec.n_det - 1) / 2.0
-    g = g * (full / part)
-    # strictly positive, so that no voxel is left without a penalty on x
-    return np.maximum(g, 1e-3 * g.max())
 
 
 def _gamma(x0):
@@ -119,7 +104,7 @@ def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=
     # dual: the stored complement c = 1 - y, as a list iterate (sup norm)
     ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
     ez = img_err(state["z"].cpu().numpy(), st.z)
-    # TV dual: relative L2 error (its sup-norm error, reported too, is set by
+    # TV dual: relative L2 error, and the sup norm against W_SUP_TOL (set by
     # voxels on the beta-sphere where w follows the direction of K x, whose
     # relative float32 error exceeds that of x in nearly flat regions)
     wg = state["w"].cpu().numpy().astype(np.float64)
@@ -128,6 +113,7 @@ def _run_compare(P, p, Gg, plan, g_orc, n_sub, beta, epochs, seed, name, events=
     report(f"{name} final", c_err=ec, z_err=ez, w_l2=ew2, w_inf_over_beta=ewinf, u=state["u"])
     assert max(errs) <= ITER_TOL
     assert ec <= ITER_TOL and ez <= ITER_TOL and ew2 <= ITER_TOL
+    assert beta == 0 or ewinf <= W_SUP_TOL
     assert float(np.sqrt((wg ** 2).sum(0)).max()) <= beta * (1 + 1e-6)
     assert state["u"] == epochs * 2 * n_sub
     return x, x_o
@@ -301,7 +287,7 @@ def test_branches_in_isolation(P, which):
         ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
         ktw = img_err(-P.tv_div(state["w"]).cpu().numpy(), oracle.grad_adjoint(st.w)) if st.w.any() else 0.0
         report(f"{which} {name}", x_err=ex, c_err=ec, w_inf_over_beta=ew, w_l2=ew2, KTw_err=ktw)
-        assert ex <= ITER_TOL and ec <= ITER_TOL and ktw <= ITER_TOL
+        assert ex <= ITER_TOL and ec <= ITER_TOL and ktw <= ITER_TOL and ew <= W_SUP_TOL
 
 
 def test_checkpoint_resume(P):

@@ -227,6 +227,40 @@ def test_lm_equals_sinogram_subsets_unit_counts(orc):
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
 
 
+def test_primal_step_rule_with_n_subsets(orc):
+    """Pins the 1/n of Eq. lm_stepsizes, T_k = rho p_k / (gamma (P^T 1)/n),
+    for n > 1 against the sinogram rule of Algorithm 1, which sums each
+    subset's own rows, T_k = rho p_k / (gamma P_k^T 1).  A sinogram made of
+    n copies of every bin, subset k = copy k, has P_k^T 1 = P^T 1 / n
+    exactly (P^T 1 summed over the whole sinogram), so sinogram SPDHG with
+    its own rule must coincide with LM-SPDHG given that sinogram's P^T 1 as
+    g.  Event e lies in copy e mod n, as the interleaved listmode subsets
+    put it; all counts are 1.  (With the 1/n dropped, T would be n times
+    smaller and the two runs would part after the first update.)"""
+    p, ev, s, x0 = tiny_problem(dup=False, n_events=300)
+    G = orc.Geometry.from_problem(p)
+    bins, boe, d1 = _sino_setup(orc, p, ev)
+    assert d1.max() == 1
+    n = 3
+    M = len(bins)
+    P1 = orc.dense_matrix(G, bins)
+    P = np.tile(P1, (n, 1))                      # row c M + b: copy c of bin b
+    row = (np.arange(len(ev)) % n) * M + boe     # event e -> copy e mod n
+    d = np.zeros(n * M)
+    d[row] = 1.0
+    sb = np.full(n * M, 0.05)
+    bos = [np.arange(c * M, (c + 1) * M) for c in range(n)]
+    g = P.sum(axis=0).reshape(G.shape)           # P^T 1 of the sinogram = n orc.sens(G)
+    np.testing.assert_allclose(g, n * orc.sens(G), rtol=1e-12, atol=0)
+    gamma, rho, beta = 3 / x0.max(), 0.999, 0.05
+    seq = lmsynth.subset_sequence(6, 0, 60, n)
+    assert (seq < n).sum() > 10
+    x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta)
+    # the sinogram run derives T from its subsets (T=None)
+    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape)
+    np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
+
+
 # ------------------------------------------------------------ P11: counts
 
 
@@ -286,3 +320,49 @@ def test_cost_decreases(orc):
         costs.append(orc.cost(G, x, ev, s, g, beta))
     assert costs[-1] < c0
     assert costs[-1] <= min(costs[:3]) + 1e-9 * abs(c0)
+
+
+# ------------------------------------- conditioning of the TV dual w
+
+
+def test_tv_dual_sup_norm_follows_rounding_of_the_state(orc):
+    """How far float32 rounding alone moves the iterates of Algorithm 2 on
+    the 2D workload (28 subsets, TV beta 0.03): two oracle runs with the
+    same inputs and sequence, one of which rounds its state (x, z, zbar,
+    w, 1 - y) to float32 after every update.  After 5 epochs x moves by
+    ~1e-6 of its maximum and w by ~1e-5 in relative L2, but w moves by
+    ~1e-3 beta in sup norm: on the beta-sphere w follows the direction of
+    K x, a difference of nearly equal values of x in flat regions, whose
+    relative error is far above that of x.  This fixes the sup-norm
+    tolerance of w in the GPU parity tests (1e-2 beta, about ten times what
+    the rounding of the stored state alone produces here) and keeps the other
+    iterates at the 1e-4 bound."""
+    import copy
+    from tests.helpers import problem_2d
+    p = problem_2d()
+    G = orc.Geometry.from_problem(p)
+    g = orc.sens(G).astype(np.float32).astype(np.float64)
+    n, beta, rho = 28, 0.03, 0.999
+    gamma = float(np.float32(3.0 / float(p.x0.max())))
+    s = p.s.astype(np.float64)
+    su = orc.lm_setup(G, p.events, n, g, gamma, rho)
+    a = orc.lm_init(G, p.events, s, su, p.x0)
+    b = copy.deepcopy(a)
+    f32 = lambda v: v.astype(np.float32).astype(np.float64)
+    w_sup = []
+    for ep in range(5):
+        for i in lmsynth.subset_sequence(2000, ep * 2 * n, 2 * n, n):
+            orc.lm_update(G, p.events, s, su, a, int(i), n, beta)
+            orc.lm_update(G, p.events, s, su, b, int(i), n, beta)
+            b.x, b.z, b.zbar, b.w, b.y = f32(b.x), f32(b.z), f32(b.zbar), f32(b.w), 1.0 - f32(1.0 - b.y)
+        w_sup.append(float(np.abs(a.w - b.w).max() / beta))
+    dx = float(np.abs(a.x - b.x).max() / np.abs(a.x).max())
+    dz = float(np.abs(a.z - b.z).max() / np.abs(a.z).max())
+    dw2 = float(np.linalg.norm(a.w - b.w) / np.linalg.norm(a.w))
+    print(f"rounded state after 5 epochs: x {dx:.2e}, z {dz:.2e}, w rel. L2 {dw2:.2e}, "
+          f"w sup / beta per epoch {['%.1e' % v for v in w_sup]}")
+    assert dx < 1e-5 and dz < 1e-5 and dw2 < 1e-4
+    # the sup norm of w is two to three orders of magnitude more sensitive
+    assert max(w_sup) > 100 * dx
+    # the GPU tolerance of 1e-2 beta stays well above this figure
+    assert 1e-4 < max(w_sup) < 2e-3
