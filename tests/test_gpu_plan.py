@@ -533,3 +533,34 @@ def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm):
         ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
         report(f"mixed updates {shape} dtv={dtv} fwhm={fwhm} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
         assert max(ex, ez, ezb, ec, ew) <= ITER_TOL
+
+
+def test_setters_on_a_plan_that_computed_g(P):
+    """A plan created with g = NULL computed g = G^T 1 itself.  Per-event
+    factors are refused (the sensitivity of diag(m) P sums m over every LOR,
+    which the event list cannot give); a resolution model replaces g by
+    B G^T 1, the sensitivity of G B, and T follows it; 2 epochs then match
+    the oracle run with that g."""
+    p = problem_2d()
+    Go = oracle.Geometry.from_problem(p)
+    Gg, plan = _plan(P, p, 28, None, 0.03)
+    m = torch.full((len(p.events),), 0.5, device="cuda")
+    with pytest.raises(P.LMError) as ei:
+        plan.set_event_factors(m)
+    assert ei.value.code == -5
+    fwhm = (2.5, 2.0, 0.0)
+    plan.set_resolution(fwhm)
+    g_want = oracle.blur(sens_2d(), fwhm)
+    g, T = plan.images()
+    eg = img_err(g.cpu().numpy(), g_want)
+    Tw = RHO / (2 * _gamma(p.x0) * np.maximum(g_want, oracle.grad_norm(Go.shape)))
+    eT = img_err(T.cpu().numpy(), Tw)
+    # a second model replaces the first (g is blurred from G^T 1 again)
+    plan.set_resolution((0.0, 0.0, 0.0))
+    g0, _ = plan.images()
+    e0 = img_err(g0.cpu().numpy(), sens_2d())
+    plan.set_resolution(fwhm)
+    report("plan-computed g under set_resolution", g_err=eg, T_err=eT, g_after_reset=e0)
+    assert eg <= ITER_TOL and eT <= ITER_TOL and e0 <= ITER_TOL
+    g_in = g.cpu().numpy().astype(np.float64)
+    _run_compare(P, p, Gg, plan, g_in, 28, 0.03, 2, 2008, "2d plan-computed g, resolution model", fwhm=fwhm)
