@@ -562,5 +562,5 @@ def test_setters_on_a_plan_that_computed_g(P):
     plan.set_resolution(fwhm)
     report("plan-computed g under set_resolution", g_err=eg, T_err=eT, g_after_reset=e0)
     assert eg <= ITER_TOL and eT <= ITER_TOL and e0 <= ITER_TOL
-    g_in = g.cpu().numpy().astype(np.float64)
-    _run_compare(P, p, Gg, plan, g_in, 28, 0.03, 2, 2008, "2d plan-computed g, resolution model", fwhm=fwhm)
+    # the oracle runs with its own B G^T 1 (the plan keeps the one it computed)
+    _run_compare(P, p, Gg, plan, g_want, 28, 0.03, 2, 2008, "2d plan-computed g, resolution model", fwhm=fwhm)
