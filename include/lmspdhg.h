@@ -93,6 +93,20 @@ const char *lm_last_error(void);
 int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out,
            void *stream);
 
+/* lm_fwd for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result as lm_fwd, but the bricked copy of x goes to a scratch
+ * array that the library holds in every device's memory from the moment
+ * its code is loaded there until the process ends (64 MiB per device), so
+ * the call allocates nothing.  LM_EINVAL when the image needs more than
+ * 2^24 floats in the 4x4x4 brick layout (e.g. beyond 512 x 512 x 64 voxels),
+ * when `stream` belongs to a device other than the current one, or for the
+ * arguments lm_fwd rejects.  Every call on a device shares its scratch:
+ * calls that overlap on one device (other streams, other host threads)
+ * race, and the caller must order them. */
+int lm_fwd_noalloc(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out,
+                   void *stream);
+
 /* Listmode back projection, the adjoint of lm_fwd: img += (P^LM)^T v.  It
  * ACCUMULATES (FP32 atomics, so the summation order is not fixed); the
  * caller zeroes img.  v: float[n].  Events that are out of range or have

@@ -31,6 +31,7 @@ _GP = ctypes.POINTER(LMGeom)
 SIGNATURES = {
     "lm_last_error": (ctypes.c_char_p, []),
     "lm_fwd": (ctypes.c_int, [_GP, _VP, _VP, _I64, _VP, _VP]),
+    "lm_fwd_noalloc": (ctypes.c_int, [_GP, _VP, _VP, _I64, _VP, _VP]),
     "lm_back": (ctypes.c_int, [_GP, _VP, _VP, _I64, _VP, _VP]),
     "lm_sens": (ctypes.c_int, [_GP, _VP, _VP]),
     "lm_validate_events": (ctypes.c_int, [_GP, _VP, _I64, ctypes.POINTER(ctypes.c_int64), _VP]),

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "lm_device.hpp"
 #include "lm_host.hpp"
@@ -392,6 +393,46 @@ int launch_data_update(const GeomDev &g, const float *x, const int4 *rec, const 
 }  // namespace lmk
 
 // --------------------------------------------------------------------------
+// Scratch of lm_fwd_noalloc: the bricked copy of the caller's image lives in
+// a file-scope device array (64 MiB on every device the library runs on,
+// held until the process ends) instead of a stream-ordered allocation.  In
+// host code `scratch` names a host-side stand-in, not device memory: kernels
+// get the address that hipGetSymbolAddress returns for the device.
+
+constexpr long long kNoAllocScratchFloats = 1LL << 24;
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which must be the
+// device of `st`), looked up once per device with that device current.
+int noalloc_scratch(hipStream_t st, float **out) {
+  int dev = -1;
+  LM_TRY_HIP(hipGetDevice(&dev));
+  LM_REQUIRE(dev >= 0 && dev < kMaxDevices, LM_EINVAL, "device %d beyond the %d the library serves", dev,
+             kMaxDevices);
+  if (st != nullptr) {
+    hipDevice_t sdev = -1;
+    LM_TRY_HIP(hipStreamGetDevice(st, &sdev));
+    LM_REQUIRE(sdev == dev, LM_EINVAL, "stream of device %d, but device %d is current", (int)sdev, dev);
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    LM_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<float *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LM_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
 // C ABI
 
 extern "C" {
@@ -408,6 +449,25 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
   if (int rc = b.alloc(g, st)) return rc;
   if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, x, b.p, st)) return rc;
   return launch_fwd(g, b.p, ev, n, out, st);
+}
+
+int lm_fwd_noalloc(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out, void *stream) {
+  lmh::clear_error();
+  GeomDev g;
+  if (int rc = lmh::make_geom(G, &g)) return rc;
+  LM_REQUIRE(n >= 0, LM_EINVAL, "negative event count");
+  LM_REQUIRE(n == 0 || (x && ev && out), LM_EINVAL, "NULL array");
+  g.lay = lmh::brick_layout(g.n);
+  const long long need = layout_size(g.lay);
+  LM_REQUIRE(need <= kNoAllocScratchFloats, LM_EINVAL,
+             "the image takes %lld floats in brick layout, beyond the %lld of lm_fwd_noalloc's scratch", need,
+             kNoAllocScratchFloats);
+  if (n == 0) return LM_OK;
+  hipStream_t st = lmh::as_stream(stream);
+  float *scr = nullptr;
+  if (int rc = noalloc_scratch(st, &scr)) return rc;
+  if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, x, scr, st)) return rc;
+  return launch_fwd(g, scr, ev, n, out, st);
 }
 
 int lm_back(const lm_geom *G, const float *v, const int16_t *ev, int64_t n, float *img, void *stream) {

@@ -121,3 +121,11 @@ def test_new_entry_points_check_arguments_first(lib):
     assert L.lm_plan_set_event_factors(None, P_, None) == lib.LM_EINVAL
     assert L.lm_plan_set_resolution(None, f3, None) == lib.LM_EINVAL
 
+
+def test_noalloc_size_limit_host_only(lib):
+    """lm_fwd_noalloc refuses an image beyond its scratch array before any
+    device work (the pointers are never dereferenced)."""
+    L = lib.load()
+    g = _geom(lib, n=(512, 512, 72))
+    assert L.lm_fwd_noalloc(ctypes.byref(g), 0x1000, 0x1000, 10, 0x1000, None) == lib.LM_EINVAL
+    assert b"scratch" in L.lm_last_error()
