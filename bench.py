@@ -661,7 +661,8 @@ def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS, max_
         "peak_hbm_bytes": int(srv.peak_bytes),
         "sequential": {"p50_s": round(float(np.percentile(lat_seq, 50)), 4),
                        "p99_s": round(float(np.percentile(lat_seq, 99)), 4),
-                       "events_per_s": round(work / service.sum(), 1),
+                       "events_per_s": round(work / fin, 1),
+                       "busy_events_per_s": round(work / service.sum(), 1),
                        "makespan_s": round(float(fin), 3)},
         "burst": {"makespan_s": round(t_burst, 3), "events_per_s": round(work / t_burst, 1),
                   "p99_s": round(float(np.percentile([r.latency for r in bres], 99)), 4),
@@ -673,14 +674,18 @@ def serving_leg(torch, P, lmsynth, G3, g3, p3, n_req: int = SERVE_REQUESTS, max_
 # --------------------------------------------------------------------------- large
 
 
-def large_leg(args, torch, P, lmsynth):
+def large_leg(args, torch, P, lmsynth, passes: int, warmup: int):
+    """The long static frame: 5e8 events on the 300x300x96 image, presented
+    sorted by dominant axis.  `warmup` untimed and `passes` timed lm_fwd +
+    lm_back passes over all events (lm_back takes its by-line path for such
+    a list), then one LM-SPDHG epoch (224 subsets) after a warm-up epoch."""
     dev = torch.device("cuda", 0)
-    n_events = args.events or LARGE_EVENTS
+    n_events = args.large_events or LARGE_EVENTS
     t0 = time.perf_counter()
     p = lmsynth.simulate_3d(lmsynth.config_3d_large(), n_prompts=n_events, seed=LARGE_SEED, progress=log)
     # the long static frame's events arrive sorted by dominant axis
     lmsynth.sort_by_dominant_axis(p)
-    log(f"generated {len(p.events)} events (sorted by dominant axis) in {time.perf_counter() - t0:.1f} s")
+    log(f"large: generated {len(p.events)} events (sorted by dominant axis) in {time.perf_counter() - t0:.1f} s")
     G = P.Geometry.from_problem(p, device=dev)
     ev = G.events(p.events)
     s = torch.as_tensor(p.s, device=dev)
@@ -691,14 +696,14 @@ def large_leg(args, torch, P, lmsynth):
     g = P.lm_sens(G)
     torch.cuda.synchronize()
     t_sens = time.perf_counter() - t0
-    log(f"lm_sens: {t_sens:.2f} s")
+    log(f"large: lm_sens {t_sens:.2f} s")
 
     out = torch.empty(N, device=dev)
     v = torch.ones(N, device=dev)
     img = G.zeros()
     stream = torch.cuda.current_stream(dev)
     tf, tb = [], []
-    for k in range(args.warmup + args.steps):
+    for k in range(warmup + passes):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         img.zero_()
         e[0].record(stream)
@@ -707,14 +712,13 @@ def large_leg(args, torch, P, lmsynth):
         P.lm_back(G, v, ev, img)
         e[2].record(stream)
         torch.cuda.synchronize()
-        if k >= args.warmup:
+        if k >= warmup:
             tf.append(e[0].elapsed_time(e[1]))
             tb.append(e[1].elapsed_time(e[2]))
-        log(f"pass {k}: lm_fwd {e[0].elapsed_time(e[1]):.1f} ms, lm_back {e[1].elapsed_time(e[2]):.1f} ms")
+        log(f"large: pass {k}: lm_fwd {e[0].elapsed_time(e[1]):.1f} ms, lm_back {e[1].elapsed_time(e[2]):.1f} ms")
     del out, v, img
     t_fwd, t_back = float(np.mean(tf)), float(np.mean(tb))
     t_pass = t_fwd + t_back
-    value = N / (t_pass * 1e-3)
 
     gamma = float(np.float32(3.0 / float(p.x0.max())))
     t0 = time.perf_counter()
@@ -722,7 +726,7 @@ def large_leg(args, torch, P, lmsynth):
     plan.init(x)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    log(f"plan + init: {t_plan:.2f} s")
+    log(f"large: plan + init {t_plan:.2f} s")
     seq0 = lmsynth.subset_sequence(LARGE_SEQ_SEED, 0, 2 * N_SUB, N_SUB)
     seq1 = lmsynth.subset_sequence(LARGE_SEQ_SEED, 2 * N_SUB, 2 * N_SUB, N_SUB)
     plan.epoch(x, seq0)
@@ -734,37 +738,36 @@ def large_leg(args, torch, P, lmsynth):
     t_epoch = time.perf_counter() - t0
     timing = plan.get_timing() if args.timing_every > 0 else None
     plan.destroy()
-    log(f"epoch: {t_epoch:.3f} s")
+    del plan, ev, s, x, g
+    torch.cuda.empty_cache()
+    log(f"large: epoch {t_epoch:.3f} s")
     kernels = None
     if timing:
         kernels = {k: {"us_avg": round(1e3 * ms / c, 2), "timed_launches": c} for k, (ms, c) in timing.items() if c}
-
-    roof = roofline("back", BYTES_PER_EVENT_PROJ * N, t_back * 1e3)
-    return {
-        "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
-        "value": round(value, 1),
-        "unit": "events/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(t_pass, 3),
-        "s_per_epoch": round(t_epoch, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "3d_672x96_300x300x96: 5e8 TOF events (30% contamination) sorted by dominant "
-                               "axis; one lm_fwd + lm_back pass per step, then one LM-SPDHG epoch (224 subsets)",
-                   "events": N, "subsets": N_SUB, "image": list(G.shape)},
+    # algorithmic bytes: each call reads the 10-byte events and writes (lm_fwd)
+    # or reads (lm_back) 4 bytes per event
+    roof_fwd = roofline("fwd", BYTES_PER_EVENT_PROJ * N, t_fwd * 1e3)
+    roof_back = roofline("back", BYTES_PER_EVENT_PROJ * N, t_back * 1e3)
+    a_pass = 2 * BYTES_PER_EVENT_PROJ * N / (t_pass * 1e-3) / 1e9
+    res = {
+        "workload": "3d_672x96_300x300x96: 5e8 TOF events (30% contamination) sorted by dominant axis",
+        "events": N, "subsets": N_SUB, "image": list(G.shape), "passes": passes, "warmup": warmup,
+        "value": round(N / (t_pass * 1e-3), 1), "unit": "events/s (lm_fwd + lm_back pass)",
+        "pass_ms": round(t_pass, 3), "s_per_epoch": round(t_epoch, 4),
         "pass": {"fwd_ms": round(t_fwd, 2), "back_ms": round(t_back, 2),
                  "fwd_events_per_s": round(N / (t_fwd * 1e-3), 1),
-                 "back_events_per_s": round(N / (t_back * 1e-3), 1),
-                 "algorithmic_GBs": round(2 * BYTES_PER_EVENT_PROJ * N / (t_pass * 1e-3) / 1e9, 1)},
-        "roofline": roof,
+                 "back_events_per_s": round(N / (t_back * 1e-3), 1)},
+        "roofline": {"kernel": "lm_fwd + lm_back", "bound": "hbm", "achieved": round(a_pass, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a_pass / HBM_PEAK_GBS, 5),
+                     "traffic": (None if roof_fwd["traffic"] is None or roof_back["traffic"] is None
+                                 else int(roof_fwd["traffic"] + roof_back["traffic"])),
+                     "bytes_per_pass": int(2 * BYTES_PER_EVENT_PROJ * N)},
+        "roofline_fwd": roof_fwd,
+        "roofline_back": roof_back,
         "kernels": kernels,
         "setup_s": {"lm_sens": round(t_sens, 3), "plan_create_init": round(t_plan, 3)},
-    }, p
+    }
+    return res, p
 
 
 def main() -> int:
@@ -772,8 +775,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("epoch", "large"), default="epoch")
-    ap.add_argument("--events", type=int, default=0, help="event count (0: the workload's own)")
+    ap.add_argument("--workload", choices=("epoch", "large"), default="epoch",
+                    help="epoch: every leg (the 1e7-event epoch is the JSON line's value); large: the 5e8-event "
+                         "long frame alone")
+    ap.add_argument("--events", type=int, default=0, help="event count of the epoch workload (0: 1e7)")
+    ap.add_argument("--large-events", type=int, default=0, help="event count of the long frame (0: 5e8)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 5e8-event long frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--timing-every", type=int, default=8,
@@ -791,7 +798,16 @@ def main() -> int:
     import paper_2201_05497_amd as P
 
     if args.workload == "large":
-        out, p = large_leg(args, torch, P, lmsynth)
+        large, p = large_leg(args, torch, P, lmsynth, passes=args.steps, warmup=args.warmup)
+        out = {"metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
+               "value": large["value"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": large["pass_ms"], "s_per_epoch": large["s_per_epoch"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic",
+               "config": {"workload": large["workload"] + "; one lm_fwd + lm_back pass per step, then one "
+                                                          "LM-SPDHG epoch (224 subsets)",
+                          "events": large["events"], "subsets": N_SUB, "image": large["image"]},
+               "roofline": large["roofline"], "large": large}
         cpu = None
         if not args.no_cpu_baseline:
             t0 = time.perf_counter()
@@ -811,6 +827,18 @@ def main() -> int:
             # own input (no GPU output is ever fed to the oracle)
             cpu = cpu_baseline(p, np.ones(G.shape))
             log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
+        del G, g, p
+        torch.cuda.empty_cache()
+        if not args.no_large:
+            # the long frame: a few passes whatever --steps says, to keep the run short
+            large, pl = large_leg(args, torch, P, lmsynth, passes=min(args.steps, 5), warmup=min(args.warmup, 2))
+            if not args.no_cpu_baseline:
+                t0 = time.perf_counter()
+                large["cpu_baseline"] = cpu_baseline_pass(pl)
+                log(f"cpu baseline (long frame pass): {large['cpu_baseline']['value']:.3e} events/s "
+                    f"({time.perf_counter() - t0:.1f} s)")
+            del pl
+            out["large"] = large
     out["cpu_baseline"] = cpu
     if args.calibrate_copy:
         calibrate_copy(torch, torch.device("cuda", 0))
