@@ -34,6 +34,7 @@
 #include "lm_dtv.hpp"
 #include "lm_host.hpp"
 #include "lm_image.hpp"
+#include "lm_tiles.hpp"
 
 // --------------------------------------------------------------------------
 // error reporting
@@ -89,6 +90,8 @@ struct lm_plan {
   // B dz after them, and two temporaries of the separable passes
   lmk::Blur blur{};
   float *xb = nullptr, *dzb = nullptr, *bt1 = nullptr, *bt2 = nullptr;
+  // data updates by image tile (3D plans whose segment lists fit)
+  lmk::TilePlan tiles;
   // the plan computed g = G^T 1 itself (lm_plan_create with g = NULL); g0
   // keeps that image when a resolution model later replaces g by B g0
   bool g_internal = false;
@@ -369,7 +372,9 @@ int lm_plan_bytes_ex(const lm_geom *G, int64_t n_ev, int32_t n_sub, int32_t part
   const int ncomp = G->n[2] > 1 ? 3 : 2;
   const long long E = lmk::layout_size(lmh::brick_layout(G->n));
   const Sizes s = plan_sizes(n_ev, n_sub, lmh::nvox_of(G->n), E, ncomp);
-  size_t extra = 0;
+  lmk::GeomDev gb = g;
+  gb.lay = lmh::brick_layout(G->n);
+  size_t extra = lmk::tile_bytes_bound(gb, n_ev, n_sub);
   // allocations of the optional parts (each with the one-element minimum of
   // the plan's allocator)
   if (parts & LM_PART_DTV) extra += 2 * (size_t)E * ncomp * sizeof(float);
@@ -508,6 +513,9 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   hipLaunchKernelGGL(k_step_T, dim3(grid_for(E)), dim3(kBlock), 0, st, p->gimg, p->T, (float)(rho / (2.0 * gamma)),
                      (float)p->knorm, E);
   step(hipGetLastError(), "step T");
+  // the tile lists of the data updates (synchronous; the per-event path
+  // stays when they do not fit)
+  if (rc == LM_OK && N > 0) rc = lmk::build_tiles(p->g, p->rec, p->off, p->tiles, p->allocs, st);
   step(hipStreamSynchronize(st), "plan create");
   free_tmp();
   if (rc != LM_OK) return fail(rc);
@@ -574,7 +582,34 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
     const bool fuse = u + 1 < n_updates;
     if (i < p->nsub) {
       const long long o = p->off[i], c = p->off[i + 1] - p->off[i];
-      if (!p->blur.on) {
+      if (p->tiles.on && !p->blur.on) {
+        // by tile: forward, prox and records, then the back projection
+        // fused with z / zbar and the next primal step
+        if (int rc = timed(p, LM_K_DATA, st, [&] {
+              return lmk::launch_tile_fwd(p->g, p->tiles, xi, p->rec, p->S, p->mu, p->c, o, c, st);
+            }))
+          return rc;
+        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
+              return lmk::launch_tile_back(p->g, p->tiles, i, p->z, xi, p->T, p->zbar, nullptr, inv_p_data, fuse,
+                                           st);
+            }))
+          return rc;
+      } else if (p->tiles.on) {
+        // P = G B by tile: the update projects B x and writes its whole back
+        // projection to dz, which the blur passes take to z
+        if (int rc = timed(p, LM_K_DATA, st, [&] {
+              int r = lmk::launch_blur(p->G.n, p->lay, E, p->blur, xi, p->xb, p->bt1, p->bt2, st);
+              if (!r) r = lmk::launch_tile_fwd(p->g, p->tiles, p->xb, p->rec, p->S, p->mu, p->c, o, c, st);
+              return r ? r : lmk::launch_tile_back(p->g, p->tiles, i, p->z, xi, p->T, p->zbar, p->dz, inv_p_data,
+                                                   fuse, st);
+            }))
+          return rc;
+        if (int rc = timed(p, LM_K_DUAL_IMAGE, st, [&] {
+              return lmk::launch_blur_dual_image(p->G.n, p->lay, E, p->blur, p->dz, p->bt1, p->bt2, p->z, xi, p->T,
+                                                 p->zbar, inv_p_data, fuse, st);
+            }))
+          return rc;
+      } else if (!p->blur.on) {
         if (int rc = timed(p, LM_K_DATA, st, [&] {
               return lmk::launch_data_update(p->g, xi, p->rec + o, p->S + o, p->mu + o, p->c + o, p->dz, c, st);
             }))

@@ -1,0 +1,576 @@
+// The data update of LM-SPDHG (Algorithm 2, data-subset branch: forward
+// projection, dual prox of Eq. proxD, back projection of the dual
+// increments, z / zbar step) by image tile, for 3D plans.
+//
+// The per-event kernel (k_data_update) adds each event's back projection
+// into dz with FP32 atomics.  On gfx950 those atomics are executed beyond
+// the L2 at about 2e10 requests/s, one request per 64-byte sector that the
+// lanes of an instruction share: ~47 requests per event, most of a data
+// update's time.  Here the subsets are fixed when the plan is created, so
+// the back projection of every subset is binned once by 8x8x8-voxel tile
+// (2x2x2 bricks): a "segment" is an event whose samples reach a tile, the
+// tile of its samples on 8 consecutive planes along its dominant axis.  An
+// update then runs in two kernels:
+//
+//   phase 1, per event (8 lanes per event, as the forward projector):
+//     q = (P x)_e + s_e, the dual prox, c = 1 - y updated, and one 80-byte
+//     record per segment of the event (its ray coefficients and cf w_j of
+//     its samples on the tile's 8 planes, cf = L dy / mu), the records of
+//     an event in a row;
+//   phase 2, one workgroup per tile: every wavefront takes the tile's
+//     records two at a time through the tile's list of record numbers
+//     (lanes = 8 planes x 4 bilinear corners per record; the list entries
+//     two steps ahead and the records one step ahead are loaded while the
+//     current ones are added)
+//     into its own LDS copies of the tile with plain read-add-writes (the
+//     32 lanes of a record touch distinct voxels); the copies are summed and
+//     the tile's voxels, loaded at the start, take the z / zbar step and the
+//     fused primal step of the next update.  No global atomics, and dz never
+//     goes to memory.
+//
+// The per-sample arithmetic (interpolation coordinates, bilinear weights,
+// TOF weights, their products) is that of the per-event kernels, so the
+// results differ from them only in the order of the float32 additions.
+// Tiles are launched hottest first (most segments over all subsets), so
+// the long ones do not trail at the end of a launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "lm_device.hpp"
+#include "lm_host.hpp"
+#include "lm_tiles.hpp"
+
+using namespace lmk;
+
+namespace {
+
+constexpr int kTE = 8;                 // tile edge, voxels
+constexpr int kTV = kTE * kTE * kTE;   // voxels per tile
+constexpr int kWaves2 = 16;            // wavefronts per phase-2 workgroup
+constexpr int kBlock2 = 64 * kWaves2;
+constexpr int kLanes1 = 8;             // lanes per event in phase 1
+constexpr int kBlock1 = 256;
+constexpr int kMaxJ8 = 16;             // phase 1 caches up to 16 samples per lane
+// The tile path runs when the largest subset has at least this many events
+// per tile: a workgroup's fixed cost (its LDS copies, the latency of its
+// first records and of its voxels) must be shared by enough segments.  On
+// the 200x200x96 image (7500 tiles) with 4.5e4 events per subset (6 per
+// tile) the two paths take the same time per data update (141 against 137
+// us); on 300x300x96 with 2.2e6 events per subset (128 per tile) the tile
+// path takes 6.4 ms against 7.4 ms.
+constexpr long long kMinEventsPerTile = 32;
+
+// Calls f(tile) for every tile that a corner of a sample of ray r on planes
+// [8 ta, 8 ta + 7] can reach, for every ta the ray visits.  The coordinate
+// of a sample, fmaf(j, V, F), is monotonic in j, so its range over a chunk
+// of planes is that of the chunk's end samples.
+template <class F>
+__device__ __forceinline__ void for_each_segment(const Ray &r, const TileGeom &tg, F f) {
+  if (r.nplanes <= 0) return;
+  const int a = r.a;
+  const int last = r.m0 + r.nplanes - 1;
+  for (int ta = r.m0 / kTE; ta <= last / kTE; ++ta) {
+    const int jlo = max(0, ta * kTE - r.m0), jhi = min(r.nplanes - 1, ta * kTE + kTE - 1 - r.m0);
+    const float u1a = fmaf((float)jlo, r.V1, r.F1), u1b = fmaf((float)jhi, r.V1, r.F1);
+    const float u2a = fmaf((float)jlo, r.V2, r.F2), u2b = fmaf((float)jhi, r.V2, r.F2);
+    const int f1a = r.I1 + (int)floorf(u1a), f1b = r.I1 + (int)floorf(u1b);
+    const int f2a = r.I2 + (int)floorf(u2a), f2b = r.I2 + (int)floorf(u2b);
+    const int lo1 = max(min(f1a, f1b), 0), hi1 = min(max(f1a, f1b) + 1, r.n1 - 1);
+    const int lo2 = max(min(f2a, f2b), 0), hi2 = min(max(f2a, f2b) + 1, r.n2 - 1);
+    if (lo1 > hi1 || lo2 > hi2) continue;
+    for (int t1 = lo1 / kTE; t1 <= hi1 / kTE; ++t1)
+      for (int t2 = lo2 / kTE; t2 <= hi2 / kTE; ++t2) {
+        const int tx = a == 0 ? ta : t1;
+        const int ty = a == 0 ? t1 : (a == 1 ? ta : t2);
+        const int tz = a == 2 ? ta : t2;
+        f((tz * tg.nty + ty) * tg.ntx + tx);
+      }
+  }
+}
+
+// Segments of one subset's events: per (subset, tile) and per event.
+__global__ __launch_bounds__(256) void k_tile_count(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long n,
+                                                    unsigned *cnt, unsigned *ecnt) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int4 rc = rec[e];
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
+  unsigned q = 0;
+  for_each_segment(r, tg, [&](int t) {
+    atomicAdd(cnt + t, 1u);
+    ++q;
+  });
+  ecnt[e] = q;
+}
+
+// Lists, per tile, the records of the subset's segments that fall in it
+// (rank from an atomic counter: the order inside a tile is not fixed).
+// Records are numbered in event order from the subset's first event
+// (eoff[0]): event e's q-th segment is record eoff[e] - eoff[0] + q.
+__global__ __launch_bounds__(256) void k_tile_place(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long n,
+                                                    const long long *off, unsigned *fill,
+                                                    const unsigned long long *eoff, unsigned *seg) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int4 rc = rec[e];
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
+  unsigned q = (unsigned)(eoff[e] - eoff[0]);
+  for_each_segment(r, tg, [&](int t) { seg[off[t] + atomicAdd(fill + t, 1u)] = q++; });
+}
+
+// Exclusive prefix sum of cnt[0 .. n) into off[0 .. n] (64-bit); one block
+// of 1024 threads, each summing a contiguous segment.
+__global__ __launch_bounds__(1024) void k_scan64(const unsigned *cnt, long long n, long long *off) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x;
+  const long long seg = (n + 1023) / 1024;
+  const long long a = min(n, t * seg), b = min(n, a + seg);
+  long long sum = 0;
+  for (long long i = a; i < b; ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long add = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  long long run = part[t] - sum;
+  for (long long i = a; i < b; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+// Exclusive prefix sum of a long list in three launches: sums of blocks of
+// kScanB entries, their prefix (k_scan64), then the prefix inside each block.
+constexpr int kScanB = 1024;
+
+__global__ __launch_bounds__(kScanB) void k_block_sums(const unsigned *in, long long n, unsigned *bsum) {
+  __shared__ unsigned red[kScanB];
+  const long long i = (long long)blockIdx.x * kScanB + threadIdx.x;
+  red[threadIdx.x] = i < n ? in[i] : 0u;
+  __syncthreads();
+  for (int o = kScanB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kScanB) void k_block_scan(const unsigned *in, long long n, const long long *boff,
+                                                       unsigned long long *out) {
+  __shared__ unsigned long long s[kScanB];
+  const int t = threadIdx.x;
+  const long long i = (long long)blockIdx.x * kScanB + t;
+  const unsigned v = i < n ? in[i] : 0u;
+  s[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanB; o <<= 1) {  // inclusive scan
+    const unsigned long long add = t >= o ? s[t - o] : 0ull;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  if (i < n) out[i] = (unsigned long long)boff[blockIdx.x] + s[t] - v;
+  if (i == n - 1) out[n] = (unsigned long long)boff[blockIdx.x] + s[t];
+}
+
+// Phase 1: per event (8 lanes), the forward projection, the dual prox (the
+// cancellation-free form of k_data_update), and the event's segment
+// records.  Lane l takes the planes m = 8 c + l of the 8-plane chunks c the
+// ray visits, so the values of a chunk's 8 planes sit in the 8 lanes.
+template <int J8>
+__global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, int maxp, const float *__restrict__ x,
+                                                      const int4 *__restrict__ rec, const float *__restrict__ S,
+                                                      const float *__restrict__ mu, float *__restrict__ cdual,
+                                                      long long n, const unsigned long long *__restrict__ eoff,
+                                                      TileRec *__restrict__ out) {
+  const int lane = threadIdx.x % kLanes1;
+  const long long e = (long long)blockIdx.x * (kBlock1 / kLanes1) + threadIdx.x / kLanes1;
+  if (e >= n) return;
+  const int4 rc = rec[e];
+  const float Se = S[e];
+  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
+  const int off8 = r.m0 & (kTE - 1);
+  float wj[J8];
+  float acc = 0.0f;
+#pragma unroll
+  for (int jj = 0; jj < J8; ++jj) {
+    const int j = lane + jj * kLanes1 - off8;
+    wj[jj] = 0.0f;
+    if (Se != 0.0f && j >= 0 && j < r.nplanes) {
+      const Sample s = sample_at(g, r, j, g.tof_on);
+      wj[jj] = s.w;
+      acc = fmaf(s.w, gather(g, x, r, s), acc);
+    }
+  }
+  acc = group_sum<kLanes1>(acc);
+  float cf = 0.0f;
+  if (Se != 0.0f) {  // LOR misses the image: the prox leaves y unchanged
+    const float q = fmaf(r.L, acc, __int_as_float(rc.w));
+    const float c = cdual[e], me = mu[e];
+    const float sq = Se * q;
+    const float t = sq - c;
+    const float rt = sqrtf(fmaf(t, t, 4.0f * Se * me));
+    const float dy = 2.0f * Se * fmaf(q, c, -me) / (sq + c + rt);
+    if (lane == 0) cdual[e] = c - dy;
+    if (dy != 0.0f) cf = r.L * (dy / me);
+  }
+  if (r.nplanes <= 0) return;
+  // the records, in the order of for_each_segment
+  const int4 h0 = make_int4(r.m0, r.nplanes, r.a, r.I1);
+  const float4 h1 = make_float4(__int_as_float(r.I2), r.F1, r.V1, r.F2);
+  const float4 h2 = make_float4(r.V2, 0.0f, 0.0f, 0.0f);
+  TileRec *o = out + (eoff[e] - eoff[0]);  // the event's records, in a row
+  const int last = r.m0 + r.nplanes - 1;
+#pragma unroll
+  for (int jj = 0; jj < J8; ++jj) {
+    const int ta = r.m0 / kTE + jj;
+    if (ta > last / kTE) break;
+    const int jlo = max(0, ta * kTE - r.m0), jhi = min(r.nplanes - 1, ta * kTE + kTE - 1 - r.m0);
+    const float u1a = fmaf((float)jlo, r.V1, r.F1), u1b = fmaf((float)jhi, r.V1, r.F1);
+    const float u2a = fmaf((float)jlo, r.V2, r.F2), u2b = fmaf((float)jhi, r.V2, r.F2);
+    const int f1a = r.I1 + (int)floorf(u1a), f1b = r.I1 + (int)floorf(u1b);
+    const int f2a = r.I2 + (int)floorf(u2a), f2b = r.I2 + (int)floorf(u2b);
+    const int lo1 = max(min(f1a, f1b), 0), hi1 = min(max(f1a, f1b) + 1, r.n1 - 1);
+    const int lo2 = max(min(f2a, f2b), 0), hi2 = min(max(f2a, f2b) + 1, r.n2 - 1);
+    if (lo1 > hi1 || lo2 > hi2) continue;
+    const float v = (wj[jj] != 0.0f) ? cf * wj[jj] : 0.0f;
+    for (int t1 = lo1 / kTE; t1 <= hi1 / kTE; ++t1)
+      for (int t2 = lo2 / kTE; t2 <= hi2 / kTE; ++t2, ++o) {
+        if (lane == 0) {
+          o->h0 = h0;
+          o->h1 = h1;
+          o->h2 = h2;
+        }
+        o->val[lane] = v;
+      }
+  }
+}
+
+// LDS position of voxel (li, lj, lk) of a tile: its brick (2 x 2 x 2 per
+// tile, x fastest) times 64 plus its place in the brick, the order of the
+// plan's layout.
+__device__ __forceinline__ int tile_lidx(int li, int lj, int lk) {
+  const int b = ((lk >> 2) * 2 + (lj >> 2)) * 2 + (li >> 2);
+  return (b << 6) | ((lk & 3) << 4) | ((lj & 3) << 2) | (li & 3);
+}
+
+struct SegLane {
+  int4 h0;
+  float4 h1, h2;
+  float v;
+};
+
+__device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, long long k, int jp) {
+  SegLane s;
+  const TileRec *r = recs + k;
+  s.h0 = r->h0;
+  s.h1 = r->h1;
+  s.h2 = r->h2;
+  s.v = r->val[jp];
+  return s;
+}
+
+// Phase 2: one workgroup per tile; recs are the subset's records, seg the
+// record numbers of every tile, off the subset's per-tile ranges of seg
+// (the subset's first at off[0]).
+__global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, const int *__restrict__ order,
+                                                       const long long *__restrict__ off,
+                                                       const unsigned *__restrict__ seg,
+                                                       const TileRec *__restrict__ recs, float *__restrict__ z,
+                                                       float *__restrict__ x, const float *__restrict__ T,
+                                                       float *__restrict__ zbar, float *__restrict__ dz_out,
+                                                       float inv_p, int fuse) {
+  __shared__ float acc[2 * kWaves2][kTV];
+  const int tile = order[blockIdx.x];
+  const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, tz = tile / (tg.ntx * tg.nty);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const int jp = hl >> 2, corner = hl & 3;
+  // this thread's voxel of the tile in the plan's brick layout; its image
+  // values are loaded now and used at the end
+  const Layout &L = g.lay;
+  const int v = threadIdx.x;
+  const int b = (v >> 6) & 7, bi = tx * 2 + (b & 1), bj = ty * 2 + ((b >> 1) & 1), bk = tz * 2 + (b >> 2);
+  const bool mine_vox = v < kTV && bi < L.nbx && bj < L.nby && bk < L.nbz;
+  const long long gi = ((((long long)bk * L.nby + bj) * L.nbx + bi) << 6) | (v & 63);
+  float xv = 0.0f, zv = 0.0f, Tv = 0.0f;
+  if (mine_vox && !dz_out) {
+    zv = z[gi];
+    if (fuse) {
+      xv = x[gi];
+      Tv = T[gi];
+    }
+  }
+  float *all = &acc[0][0];
+  for (int i = threadIdx.x; i < 2 * kWaves2 * kTV; i += kBlock2) all[i] = 0.0f;
+  __syncthreads();
+  float *mine = acc[2 * wv + half];
+  const long long s0 = off[tile], s1 = off[tile + 1];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  constexpr long long kStep = 2 * kWaves2;
+  long long k = s0 + 2 * wv + half;
+  unsigned idx_nxt = (k + kStep < s1) ? seg[k + kStep] : 0u;
+  SegLane cur = {};
+  if (k < s1) cur = load_seg(recs, seg[k], jp);
+  for (long long kb = s0 + 2 * wv; kb < s1; kb += kStep) {
+    const long long kn = k + kStep, knn = k + 2 * kStep;
+    const unsigned idx_nn = (knn < s1) ? seg[knn] : 0u;    // two steps ahead
+    SegLane nxt = {};
+    if (kn < s1) nxt = load_seg(recs, idx_nxt, jp);       // one step ahead
+    float add = 0.0f;
+    int at = 0;
+    if (k < s1 && cur.v != 0.0f) {
+      const int m0 = cur.h0.x, np = cur.h0.y, a = cur.h0.z, I1 = cur.h0.w;
+      const int I2 = __float_as_int(cur.h1.x);
+      const float F1 = cur.h1.y, V1 = cur.h1.z, F2 = cur.h1.w, V2 = cur.h2.x;
+      const int ta = a == 0 ? tx : (a == 1 ? ty : tz);
+      const int m = ta * kTE + jp;
+      const int j = m - m0;
+      if (j >= 0 && j < np) {
+        // the sample and corner of sample_at / corner()
+        const float u1 = fmaf((float)j, V1, F1), u2 = fmaf((float)j, V2, F2);
+        const float fl1 = floorf(u1), fl2 = floorf(u2);
+        const float f1 = u1 - fl1, f2 = u2 - fl2;
+        const int c1 = I1 + (int)fl1 + (corner & 1), c2 = I2 + (int)fl2 + (corner >> 1);
+        const float wc = ((corner & 1) ? f1 : 1.0f - f1) * ((corner & 2) ? f2 : 1.0f - f2);
+        const int i = a == 0 ? m : c1;
+        const int jj = a == 0 ? c1 : (a == 1 ? m : c2);
+        const int kk = a == 2 ? m : c2;
+        const int li = i - tx * kTE, lj = jj - ty * kTE, lk = kk - tz * kTE;
+        if ((unsigned)li < (unsigned)kTE && (unsigned)lj < (unsigned)kTE && (unsigned)lk < (unsigned)kTE &&
+            i < nx && jj < ny && kk < nz && wc != 0.0f) {
+          add = cur.v * wc;
+          at = tile_lidx(li, lj, lk);
+        }
+      }
+    }
+    // the 32 lanes of a record touch distinct voxels of their own copy; a
+    // lane may read a word another lane of the wavefront wrote in the
+    // previous iteration, which the wavefront's in-order LDS operations
+    // deliver once the compiler keeps the order (the fences)
+    if (add != 0.0f) mine[at] += add;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    cur = nxt;
+    idx_nxt = idx_nn;
+    k = kn;
+  }
+  __syncthreads();
+  if (!mine_vox) return;
+  float d = 0.0f;
+#pragma unroll 8
+  for (int c = 0; c < 2 * kWaves2; ++c) d += acc[c][v];
+  if (dz_out) {
+    dz_out[gi] = d;
+    return;
+  }
+  const float zn = zv + d;
+  const float zb = fmaf(d, inv_p, zn);
+  z[gi] = zn;
+  if (fuse)
+    x[gi] = fmaxf(0.0f, fmaf(-Tv, zb, xv));
+  else
+    zbar[gi] = zb;
+}
+
+inline unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+namespace lmk {
+
+TileGeom tile_geom(const int n[3]) {
+  TileGeom t;
+  t.ntx = (n[0] + kTE - 1) / kTE;
+  t.nty = (n[1] + kTE - 1) / kTE;
+  t.ntz = (n[2] + kTE - 1) / kTE;
+  t.ntiles = t.ntx * t.nty * t.ntz;
+  return t;
+}
+
+// 3D plans (4x4x4 bricks) whose events visit few enough planes for the
+// register cache of phase 1.
+static int j8_for(int maxp) { return (maxp + kTE - 1 + kLanes1 - 1) / kLanes1; }
+
+bool tiles_supported(const GeomDev &g) {
+  if (g.n[2] < 2 || g.lay.sx != 2 || g.lay.sy != 2 || g.lay.sz != 2) return false;
+  return j8_for(lmh::max_planes(g, W_BIN)) <= kMaxJ8;
+}
+
+size_t tile_bytes_bound(const GeomDev &g, long long n, int nsub) {
+  if (!tiles_supported(g) || n <= 0) return 0;
+  const TileGeom tg = tile_geom(g.n);
+  if ((n + nsub - 1) / nsub < kMinEventsPerTile * tg.ntiles) return 0;
+  const int maxp = lmh::max_planes(g, W_BIN);
+  // tiles a chunk of 8 planes along axis a can reach along axis b: the
+  // corners span at most 7 h_a / h_b + 3 voxels
+  long long per_chunk = 1;
+  for (int a = 0; a < 3; ++a) {
+    long long m = 1;
+    for (int b = 0; b < 3; ++b) {
+      if (b == a) continue;
+      const long long span = (long long)std::floor(7.0 * g.h[a] / g.h[b]) + 3;
+      m *= (span + kTE - 2) / kTE + 1;
+    }
+    per_chunk = std::max(per_chunk, m);
+  }
+  const long long per_event = ((maxp + kTE - 2) / kTE + 1) * per_chunk;
+  const long long nmax = (n + nsub - 1) / nsub;
+  const long long nbin = (long long)nsub * tg.ntiles;
+  const size_t kept = (size_t)(n * per_event) * sizeof(unsigned) + (size_t)(n + 1) * sizeof(unsigned long long) +
+                      (size_t)(nbin + 1) * sizeof(long long) + (size_t)tg.ntiles * sizeof(int) +
+                      (size_t)(nmax * per_event) * sizeof(TileRec);
+  const size_t temporary = (size_t)nbin * sizeof(unsigned) + (size_t)n * sizeof(unsigned) +
+                           (size_t)((n + kScanB - 1) / kScanB) * (sizeof(unsigned) + sizeof(long long) + 8);
+  return kept + temporary;
+}
+
+int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, TilePlan &tp,
+                std::vector<void *> &owned, hipStream_t st) {
+  tp = TilePlan{};
+  if (!tiles_supported(g)) return LM_OK;
+  const int nsub = (int)off.size() - 1;
+  const long long N = off.back();
+  if (N == 0) return LM_OK;
+  const TileGeom tg = tile_geom(g.n);
+  long long nlargest = 0;
+  for (int i = 0; i < nsub; ++i) nlargest = std::max<long long>(nlargest, off[i + 1] - off[i]);
+  if (nlargest < kMinEventsPerTile * tg.ntiles) return LM_OK;
+  const int maxp = lmh::max_planes(g, W_BIN);
+  const long long nbin = (long long)nsub * tg.ntiles;
+  const long long nblk = (N + kScanB - 1) / kScanB;
+  // temporaries: counts per (subset, tile) and per event, block sums
+  unsigned *cnt = nullptr, *ecnt = nullptr, *bsum = nullptr;
+  long long *boff = nullptr;
+  // kept by the plan
+  long long *soff = nullptr;
+  unsigned long long *eoff = nullptr;
+  unsigned *seg = nullptr;
+  int *ord = nullptr;
+  TileRec *recs = nullptr;
+  std::vector<void *> tmp;
+  auto drop = [&](bool keep_error) {
+    for (void *q : tmp) (void)hipFreeAsync(q, st);
+    for (void *q : {(void *)soff, (void *)eoff, (void *)seg, (void *)ord, (void *)recs})
+      if (q) (void)hipFreeAsync(q, st);
+    if (!keep_error) (void)hipGetLastError();
+  };
+  auto get = [&](auto **ptr, size_t bytes, bool temporary) {
+    const hipError_t e = hipMallocAsync((void **)ptr, std::max<size_t>(bytes, 1), st);
+    if (e == hipSuccess && temporary) tmp.push_back(*ptr);
+    return e;
+  };
+  hipError_t e = get(&cnt, nbin * sizeof(unsigned), true);
+  if (e == hipSuccess) e = get(&ecnt, N * sizeof(unsigned), true);
+  if (e == hipSuccess) e = get(&bsum, nblk * sizeof(unsigned), true);
+  if (e == hipSuccess) e = get(&boff, (nblk + 1) * sizeof(long long), true);
+  if (e == hipSuccess) e = get(&soff, (nbin + 1) * sizeof(long long), false);
+  if (e == hipSuccess) e = get(&eoff, (N + 1) * sizeof(unsigned long long), false);
+  if (e != hipSuccess) {
+    drop(false);
+    return LM_OK;  // no room: the per-event path
+  }
+  auto fail = [&](hipError_t he) {
+    drop(true);
+    lmh::set_error("tile binning: %s", hipGetErrorString(he));
+    return LM_EHIP;
+  };
+  if ((e = hipMemsetAsync(cnt, 0, nbin * sizeof(unsigned), st)) != hipSuccess) return fail(e);
+  for (int i = 0; i < nsub; ++i) {
+    const long long m = off[i + 1] - off[i];
+    if (m == 0) continue;
+    hipLaunchKernelGGL(k_tile_count, dim3(blocks(m, 256)), dim3(256), 0, st, g, tg, maxp, rec + off[i], m,
+                       cnt + (long long)i * tg.ntiles, ecnt + off[i]);
+  }
+  hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, cnt, nbin, soff);
+  hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nblk), dim3(kScanB), 0, st, ecnt, N, bsum);
+  hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, bsum, nblk, boff);
+  hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nblk), dim3(kScanB), 0, st, ecnt, N, boff, eoff);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  // per-tile loads over all subsets (launch order) and the largest subset's segments
+  std::vector<long long> hoff((size_t)nbin + 1);
+  if ((e = hipMemcpyAsync(hoff.data(), soff, (nbin + 1) * sizeof(long long), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return fail(e);
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e);
+  const long long total = hoff[nbin];
+  long long rec_max = 0;
+  for (int i = 0; i < nsub; ++i)
+    rec_max = std::max(rec_max, hoff[(size_t)(i + 1) * tg.ntiles] - hoff[(size_t)i * tg.ntiles]);
+  if (rec_max >= (1LL << 32)) {
+    drop(false);
+    return LM_OK;  // record numbers relative to a subset must fit 32 bits
+  }
+  std::vector<long long> load(tg.ntiles, 0);
+  for (long long b = 0; b < nbin; ++b) load[b % tg.ntiles] += hoff[b + 1] - hoff[b];
+  std::vector<int> order(tg.ntiles);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
+  e = get(&seg, total * sizeof(unsigned), false);
+  if (e == hipSuccess) e = get(&ord, tg.ntiles * sizeof(int), false);
+  if (e == hipSuccess) e = get(&recs, rec_max * sizeof(TileRec), false);
+  if (e != hipSuccess) {
+    drop(false);
+    return LM_OK;  // no room for the segments: the per-event path
+  }
+  if ((e = hipMemcpyAsync(ord, order.data(), tg.ntiles * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemsetAsync(cnt, 0, nbin * sizeof(unsigned), st)) != hipSuccess)
+    return fail(e);
+  for (int i = 0; i < nsub; ++i) {
+    const long long m = off[i + 1] - off[i];
+    if (m == 0) continue;
+    hipLaunchKernelGGL(k_tile_place, dim3(blocks(m, 256)), dim3(256), 0, st, g, tg, maxp, rec + off[i], m,
+                       soff + (long long)i * tg.ntiles, cnt + (long long)i * tg.ntiles, eoff + off[i], seg);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  // the host order vector dies with this call
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e);
+  for (void *q : tmp) (void)hipFreeAsync(q, st);
+  for (void *q : {(void *)soff, (void *)eoff, (void *)seg, (void *)ord, (void *)recs}) owned.push_back(q);
+  tp.on = true;
+  tp.tg = tg;
+  tp.maxp = maxp;
+  tp.nseg = total;
+  tp.rec_max = rec_max;
+  tp.seg_off = soff;
+  tp.eoff = eoff;
+  tp.seg = seg;
+  tp.order = ord;
+  tp.rec = recs;
+  return LM_OK;
+}
+
+int launch_tile_fwd(const GeomDev &g, const TilePlan &tp, const float *x, const int4 *rec, const float *S,
+                    const float *mu, float *cdual, long long o, long long n, hipStream_t st) {
+  if (n == 0) return LM_OK;
+  const int jneed = j8_for(tp.maxp);
+#define LM_TF(J_)                                                                                               \
+  if (jneed <= J_) {                                                                                            \
+    hipLaunchKernelGGL((k_tile_fwd<J_>), dim3(blocks(n, kBlock1 / kLanes1)), dim3(kBlock1), 0, st, g, tp.tg,     \
+                       tp.maxp, x, rec + o, S + o, mu + o, cdual + o, n, tp.eoff + o, tp.rec);             \
+    LM_TRY_HIP(hipGetLastError());                                                                              \
+    return LM_OK;                                                                                               \
+  }
+  LM_TF(8) LM_TF(10) LM_TF(12) LM_TF(14) LM_TF(16)
+#undef LM_TF
+  lmh::set_error("no tile update kernel for %d planes per event", tp.maxp);
+  return LM_EINVAL;
+}
+
+int launch_tile_back(const GeomDev &g, const TilePlan &tp, int subset, float *z, float *x, const float *T,
+                     float *zbar, float *dz_out, float inv_p, bool fuse, hipStream_t st) {
+  const long long *off = tp.seg_off + (long long)subset * tp.tg.ntiles;
+  hipLaunchKernelGGL(k_tile_back, dim3(tp.tg.ntiles), dim3(kBlock2), 0, st, g, tp.tg, tp.order, off, tp.seg, tp.rec,
+                     z, x, T, zbar, dz_out, inv_p, fuse ? 1 : 0);
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+}  // namespace lmk

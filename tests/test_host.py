@@ -140,12 +140,17 @@ def test_plan_bytes_grow_with_events_and_image():
         assert lib.lm_plan_bytes(ctypes.byref(g), n_ev, n_sub, ctypes.byref(b)) == 0
         return b.value
 
-    a = plan_bytes(1000, (16, 16, 8))
-    assert plan_bytes(2000, (16, 16, 8)) > a
-    assert plan_bytes(1000, (32, 16, 8)) > a
+    # few events per 8x8x8 tile: the per-event data update, no tile lists
+    a = plan_bytes(1000, (16, 16, 8), n_sub=16)
+    assert plan_bytes(2000, (16, 16, 8), n_sub=16) > a
+    assert plan_bytes(1000, (32, 16, 8), n_sub=16) > a
     # per event: the record (16 B) and five 4-byte lists persist, plus the
     # hash table of plan creation
-    assert plan_bytes(2000, (16, 16, 8)) - a >= 1000 * 40
+    assert plan_bytes(2000, (16, 16, 8), n_sub=16) - a >= 1000 * 40
+    # with enough events per tile (32 per tile of the largest subset) the
+    # plan also holds the tile lists of the data updates (an upper bound)
+    t = plan_bytes(20000, (16, 16, 8), n_sub=4)
+    assert t - plan_bytes(20000, (16, 16, 8), n_sub=400) > 20000 * 4
 
 
 def test_sort_by_dominant_axis():
