@@ -175,7 +175,9 @@ def compute_sens():
 # Images are stored as integers on a grid of 2^-18 of their largest
 # magnitude (rounding error at most 1.9e-6 of the maximum, 2 % of the 1e-4
 # parity bound), differenced along x so that smooth regions compress, and
-# packed with lzma; per-event lists stay float32.
+# packed with lzma; zbar is stored as its difference from z (the last
+# update's z increment over p), on a grid of its own; per-event lists stay
+# float32.
 
 QBITS = 18
 
@@ -209,7 +211,14 @@ def pack() -> None:
         out = {}
         for k in raw.files:
             a = raw[k]
-            if a.ndim >= 2:
+            if k == "zbar" and "z" in raw.files:
+                # against z as it will be read back
+                zq, zs, zsc = _pack_image(raw["z"])
+                blob, shape, sc = _pack_image(a.astype(np.float64) - _unpack_image(zq, zs, zsc))
+                out["dq_zbar"] = blob
+                out["shape_zbar"] = shape
+                out["s_zbar"] = np.float64(sc)
+            elif a.ndim >= 2:
                 blob, shape, sc = _pack_image(a)
                 out[f"q_{k}"] = blob
                 out[f"shape_{k}"] = shape
@@ -230,8 +239,12 @@ def load(name: str) -> dict:
         if k.startswith("q_"):
             b = k[2:]
             out[b] = _unpack_image(d[k], d["shape_" + b], float(d["s_" + b]))
-        elif not (k.startswith("s_") or k.startswith("shape_")):
+        elif not (k.startswith("s_") or k.startswith("shape_") or k.startswith("dq_")):
             out[k] = d[k]
+    for k in d.files:
+        if k.startswith("dq_"):  # stored as a difference from z
+            b = k[3:]
+            out[b] = out["z"] + _unpack_image(d[k], d["shape_" + b], float(d["s_" + b]))
     return out
 
 
