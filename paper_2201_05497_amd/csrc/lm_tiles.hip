@@ -49,7 +49,7 @@ namespace {
 
 constexpr int kTE = 8;                 // tile edge, voxels
 constexpr int kTV = kTE * kTE * kTE;   // voxels per tile
-constexpr int kWaves2 = 16;            // wavefronts per phase-2 workgroup
+constexpr int kWaves2 = 8;             // wavefronts per phase-2 workgroup
 constexpr int kBlock2 = 64 * kWaves2;
 constexpr int kLanes1 = 8;             // lanes per event in phase 1
 constexpr int kBlock1 = 256;
@@ -58,10 +58,12 @@ constexpr int kMaxJ8 = 16;             // phase 1 caches up to 16 samples per la
 // per tile: a workgroup's fixed cost (its LDS copies, the latency of its
 // first records and of its voxels) must be shared by enough segments.  On
 // the 200x200x96 image (7500 tiles) with 4.5e4 events per subset (6 per
-// tile) the two paths take the same time per data update (141 against 137
-// us); on 300x300x96 with 2.2e6 events per subset (128 per tile) the tile
-// path takes 6.4 ms against 7.4 ms.
-constexpr long long kMinEventsPerTile = 32;
+// tile) a data update takes 115 us by tile (49 us phase 1, 66 us phase 2)
+// against 137 us per event (118 us, then 19 us for the z / zbar pass).
+// Workgroups of 8 wavefronts (16 LDS copies, 32 KB) run four to a CU and
+// hide each other's latency: 16 wavefronts took 92 us in phase 2, 4 took
+// 67 us.
+constexpr long long kMinEventsPerTile = 4;
 
 // Calls f(tile) for every tile that a corner of a sample of ray r on planes
 // [8 ta, 8 ta + 7] can reach, for every ta the ray visits.  The coordinate
