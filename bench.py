@@ -542,6 +542,94 @@ def leg_2d(torch, P, lmsynth, epochs: int = 10):
             "s_per_epoch": round(t, 6), "us_per_update": round(1e6 * t / (2 * n), 2)}
 
 
+# --------------------------------------------------------------------------- convergence
+
+
+CONV_SUBSETS = (28, 56, 112, 224)
+CONV_EPOCHS = (1, 2, 3, 5, 7, 10, 15, 20, 30, 50, 70, 100)
+CONV_REF_EPOCHS = 20000        # reference: LM-SPDHG with one subset (2 updates per epoch)
+CONV_REF_SUBSETS = 1
+
+
+def convergence_leg(torch, P, lmsynth):
+    """The convergence study of Section 3 on the 2D workload (the stand-in
+    for the 2D BrainWeb slice; TV beta 0.03): from the paper's warm start
+    (one listmode EM-TV iteration with 28 subsets), LM-SPDHG with 28, 56,
+    112 and 224 subsets for 100 epochs (an epoch, the paper's iteration, is
+    2n updates), with the relative cost c_rel(x) = (c(x) - c(x*)) / (c(x0) -
+    c(x*)) (c from lm_cost, the listmode Eq. 1) and PSNR(x) = 20 log10
+    (max x* / RMSE(x, x*)) along the way.  The paper's reference is 20000
+    iterations of deterministic PDHG; here x* is 20000 epochs of LM-SPDHG
+    with one subset (the data and the prior dual drawn with probability
+    1/2 each), checked against 2000 epochs with 28 subsets."""
+    dev = torch.device("cuda", 0)
+    p = lmsynth.simulate_2d(lmsynth.config_2d())
+    G = P.Geometry.from_problem(p, device=dev)
+    ev = G.events(p.events)
+    s = torch.as_tensor(p.s, device=dev)
+    g = P.lm_sens(G)
+    x0 = torch.as_tensor(p.x0, device=dev).clone()
+    P.lm_emtv(G, ev, s, g, x0, 28, 1, BETA, 20)  # warm start
+    gamma = float(np.float32(3.0 / float(x0.max())))
+    cost = lambda x: P.lm_cost(G, x, ev, s, g, BETA)[0]
+
+    def run(n, epochs, seed, checkpoints=()):
+        plan = P.Plan(G, ev, s, n, gamma, RHO, BETA, g=g)
+        x = x0.clone()
+        plan.init(x)
+        snaps = {}
+        # one call per stretch of epochs between checkpoints (at most 1000)
+        stops = sorted(set(list(checkpoints) + list(range(1000, epochs, 1000)) + [epochs]))
+        seqs, done = [], 0
+        for e in stops:
+            seqs.append((e, lmsynth.subset_sequence(seed, done * 2 * n, (e - done) * 2 * n, n)))
+            done = e
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_run = 0.0
+        for ep, seq in seqs:
+            plan.epoch(x, seq)
+            if ep in checkpoints:
+                torch.cuda.synchronize()
+                t_run += time.perf_counter() - t0
+                snaps[ep] = (x.cpu().numpy().astype(np.float64), cost(x))
+                t0 = time.perf_counter()
+        torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        plan.destroy()
+        return x, snaps, t_run
+
+    t0 = time.perf_counter()
+    xr, _, t_ref = run(CONV_REF_SUBSETS, CONV_REF_EPOCHS, 3000)
+    xr28, _, _ = run(28, 2000, 3001)
+    c_star, c_28 = cost(xr), cost(xr28)
+    c0 = cost(x0)
+    x_star = xr.cpu().numpy().astype(np.float64)
+    mx = float(np.abs(x_star).max())
+
+    def psnr(x):
+        mse = float(np.mean((x - x_star) ** 2))
+        return float("inf") if mse == 0 else 20.0 * np.log10(mx / np.sqrt(mse))
+
+    curves = {}
+    for n in CONV_SUBSETS:
+        _, snaps, t_run = run(n, max(CONV_EPOCHS), 3100 + n, CONV_EPOCHS)
+        curves[str(n)] = {"epochs": list(CONV_EPOCHS),
+                          "c_rel": [float(f"{(snaps[e][1] - c_star) / (c0 - c_star):.4g}") for e in CONV_EPOCHS],
+                          "psnr_db": [round(psnr(snaps[e][0]), 2) for e in CONV_EPOCHS],
+                          "s_per_epoch": round(t_run / max(CONV_EPOCHS), 6)}
+        log(f"convergence: {n} subsets: c_rel {curves[str(n)]['c_rel'][-1]:.3g}, "
+            f"PSNR {curves[str(n)]['psnr_db'][-1]:.1f} dB after {max(CONV_EPOCHS)} epochs")
+    out = {"workload": "2d_360_128x128: 1e5 TOF events, TV beta 0.03, warm start 1 EM-TV iteration (28 subsets)",
+           "reference": {"subsets": CONV_REF_SUBSETS, "epochs": CONV_REF_EPOCHS, "cost": c_star, "s": round(t_ref, 3),
+                         "cost_x0": c0,
+                         "check": {"subsets": 28, "epochs": 2000,
+                                   "c_rel": float(f"{(c_28 - c_star) / (c0 - c_star):.3g}"),
+                                   "psnr_db": round(psnr(xr28.cpu().numpy().astype(np.float64)), 2)}},
+           "curves": curves, "s": round(time.perf_counter() - t0, 2)}
+    return out
+
+
 # --------------------------------------------------------------------------- autograd
 
 
@@ -817,6 +905,7 @@ def main() -> int:
         out, p, G, g = epoch_leg(args, torch, P, lmsynth)
         out["warm_start"] = warm_start_leg(torch, P, G, g, p)
         out["epoch_2d"] = leg_2d(torch, P, lmsynth)
+        out["convergence"] = convergence_leg(torch, P, lmsynth)
         out["autograd"] = autograd_leg(torch, P, lmsynth)
         if not args.no_serve:
             out["served"] = serving_leg(torch, P, lmsynth, G, g, p)
