@@ -13,9 +13,10 @@
 // update then runs in two kernels:
 //
 //   phase 1, per event (8 lanes per event, as the forward projector):
-//     q = (P x)_e + s_e, the dual prox, c = 1 - y updated, and one 80-byte
+//     q = (P x)_e + s_e, the dual prox, c = 1 - y updated, and one
 //     record per segment of the event (its ray coefficients and cf w_j of
-//     its samples on the tile's 8 planes, cf = L dy / mu), the records of
+//     its samples on the tile's 8 planes, cf = L dy / mu; 64 bytes, one
+//     memory sector), the records of
 //     an event in a row;
 //   phase 2, one workgroup per tile: every wavefront takes the tile's
 //     records two at a time through the tile's list of record numbers
@@ -44,6 +45,8 @@
 #include "lm_tiles.hpp"
 
 using namespace lmk;
+
+static_assert(sizeof(TileRec) == 64, "a record is one 64-byte memory sector");
 
 namespace {
 
@@ -225,9 +228,9 @@ __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, in
   }
   if (r.nplanes <= 0) return;
   // the records, in the order of for_each_segment
-  const int4 h0 = make_int4(r.m0, r.nplanes, r.a, r.I1);
-  const float4 h1 = make_float4(__int_as_float(r.I2), r.F1, r.V1, r.F2);
-  const float4 h2 = make_float4(r.V2, 0.0f, 0.0f, 0.0f);
+  // m0 < 512 and nplanes <= 512 (image sizes up to 512)
+  const int4 h0 = make_int4(r.m0 | (r.nplanes << 10) | (r.a << 20), r.I1, r.I2, 0);
+  const float4 h1 = make_float4(r.F1, r.V1, r.F2, r.V2);
   TileRec *o = out + (eoff[e] - eoff[0]);  // the event's records, in a row
   const int last = r.m0 + r.nplanes - 1;
 #pragma unroll
@@ -248,7 +251,6 @@ __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, in
         if (lane == 0) {
           o->h0 = h0;
           o->h1 = h1;
-          o->h2 = h2;
         }
         o->val[lane] = v;
       }
@@ -265,7 +267,7 @@ __device__ __forceinline__ int tile_lidx(int li, int lj, int lk) {
 
 struct SegLane {
   int4 h0;
-  float4 h1, h2;
+  float4 h1;
   float v;
 };
 
@@ -274,7 +276,6 @@ __device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, lo
   const TileRec *r = recs + k;
   s.h0 = r->h0;
   s.h1 = r->h1;
-  s.h2 = r->h2;
   s.v = r->val[jp];
   return s;
 }
@@ -328,9 +329,9 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
     float add = 0.0f;
     int at = 0;
     if (k < s1 && cur.v != 0.0f) {
-      const int m0 = cur.h0.x, np = cur.h0.y, a = cur.h0.z, I1 = cur.h0.w;
-      const int I2 = __float_as_int(cur.h1.x);
-      const float F1 = cur.h1.y, V1 = cur.h1.z, F2 = cur.h1.w, V2 = cur.h2.x;
+      const int m0 = cur.h0.x & 1023, np = (cur.h0.x >> 10) & 1023, a = cur.h0.x >> 20;
+      const int I1 = cur.h0.y, I2 = cur.h0.z;
+      const float F1 = cur.h1.x, V1 = cur.h1.y, F2 = cur.h1.z, V2 = cur.h1.w;
       const int ta = a == 0 ? tx : (a == 1 ? ty : tz);
       const int m = ta * kTE + jp;
       const int j = m - m0;

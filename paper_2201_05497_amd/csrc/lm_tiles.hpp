@@ -19,15 +19,15 @@ struct TileGeom {
   int ntx, nty, ntz, ntiles;
 };
 
-// One segment as phase 2 reads it (80 bytes, written by phase 1; the
-// records of an event in a row): the event's plane range and interpolation coefficients
-// of setup_ray (h0 = {m0, nplanes, a, I1}, h1 = {I2, F1, V1, F2} with I2's
-// bits, h2 = {V2, 0, 0, 0}) and the values cf w_j of the samples on the
-// tile's 8 planes along the event's dominant axis (0 outside the ray;
-// cf = L dy / mu).
-struct TileRec {
+// One segment as phase 2 reads it (64 bytes, one memory sector; written
+// by phase 1, the records of an event in a row): the event's plane range
+// and interpolation coefficients of setup_ray (h0 = {m0 | nplanes << 10 |
+// a << 20, I1, I2, 0}, h1 = {F1, V1, F2, V2}) and the values cf w_j of the
+// samples on the tile's 8 planes along the event's dominant axis (0
+// outside the ray; cf = L dy / mu).
+struct __align__(64) TileRec {
   int4 h0;
-  float4 h1, h2;
+  float4 h1;
   float val[8];
 };
 
