@@ -90,6 +90,7 @@ struct Ray {
   int n1, n2;        // image size along the two other axes
   int I1, I2;        // integer parts of the interpolation coordinates at m0
   float F1, V1, F2, V2;  // u_b(m0 + j) = I_b + F_b + j V_b
+  double F1d, V1d, F2d, V2d;  // the same in double (the forward walk's coordinates)
   float A, B, D;     // TOF: vh(j) = A - j B, vl = vh - D (units of sigma sqrt 2)
   float L;           // plane length h_a |d| / |d_a|
 };
@@ -118,6 +119,7 @@ __host__ __device__ __forceinline__ Ray setup_ray(const GeomDev &g, int id1, int
   r.nplanes = 0;
   r.m0 = r.a = r.n1 = r.n2 = r.I1 = r.I2 = 0;
   r.F1 = r.V1 = r.F2 = r.V2 = r.A = r.B = r.D = r.L = 0.0f;
+  r.F1d = r.V1d = r.F2d = r.V2d = 0.0;
   const float *q1 = g.det + 3 * id1;
   const float *q2 = g.det + 3 * id2;
   const float f1x = q1[0], f1y = q1[1], f1z = q1[2];
@@ -213,8 +215,12 @@ __host__ __device__ __forceinline__ Ray setup_ray(const GeomDev &g, int id1, int
   const double i1 = floor(u1), i2 = floor(u2);
   r.I1 = (int)i1;
   r.I2 = (int)i2;
-  r.F1 = (float)(u1 - i1);
-  r.F2 = (float)(u2 - i2);
+  r.F1d = u1 - i1;
+  r.F2d = u2 - i2;
+  r.V1d = V1;
+  r.V2d = V2;
+  r.F1 = (float)r.F1d;
+  r.F2 = (float)r.F2d;
   r.V1 = (float)V1;
   r.V2 = (float)V2;
   r.L = (float)(ha * dn / fabs(da));
@@ -288,7 +294,12 @@ __host__ __device__ __forceinline__ float tof_weight(float vh, float vl, float v
   vl = fminf(fmaxf(vl, -vclip), vclip);
   const float eh = erfc_fit(fabsf(vh));
   const float el = erfc_fit(fabsf(vl));
-  const float w = (vl >= 0.0f) ? el - eh : ((vh <= 0.0f) ? eh - el : 2.0f - el - eh);
+  // selects rather than branches (same values): el - eh on the positive
+  // side, its negation eh - el on the negative side, 2 - el - eh across 0
+  const float d = el - eh;
+  const float same = (vl >= 0.0f) ? d : -d;
+  const float across = (2.0f - el) - eh;
+  const float w = (vl >= 0.0f || vh <= 0.0f) ? same : across;
   return w * inv_norm;
 }
 
@@ -351,6 +362,64 @@ __host__ __device__ __forceinline__ float gather(const GeomDev &g, const float *
   const float lo = fmaf(s.f1, v[1] - v[0], v[0]);
   const float hi = fmaf(s.f1, v[3] - v[2], v[2]);
   return fmaf(s.f2, hi - lo, lo);
+}
+
+// A voxel index of a layout is a sum of one term per axis: with brick
+// coordinate c >> s and position c & mask inside the brick,
+// vidx(L, i, j, k) = term(i) + term(j) + term(k), term(c) = (c >> s) * bs +
+// ((c & mask) << w), bs the stride of one brick along the axis (in voxels)
+// and w the in-brick shift.  The gathers below add the terms of the two
+// other axes to the dominant axis' term; a corner one voxel further along an
+// axis adds that axis' `step`, or `wrap` when it crosses into the next brick.
+struct AxisTerm {
+  int s, mask, w, bs;
+  int step, wrap;
+};
+
+__host__ __device__ __forceinline__ AxisTerm axis_term(const Layout &L, int axis) {
+  AxisTerm t;
+  t.s = sel3(axis, L.sx, L.sy, L.sz);
+  t.mask = (1 << t.s) - 1;
+  t.w = sel3(axis, 0, L.sx, L.sx + L.sy);
+  t.bs = sel3(axis, 1, L.nbx, L.nbx * L.nby) << (L.sx + L.sy + L.sz);
+  t.step = 1 << t.w;
+  t.wrap = t.bs - (t.mask << t.w);
+  return t;
+}
+
+// term(c) for c >= 0.  Both factors stay below 2^24 for images of up to
+// kMaxDim voxels per axis, so the product takes the 24-bit multiply.
+__host__ __device__ __forceinline__ int axis_index(const AxisTerm &t, int c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return (int)__umul24((unsigned)(c >> t.s), (unsigned)t.bs) + ((c & t.mask) << t.w);
+#else
+  return (c >> t.s) * t.bs + ((c & t.mask) << t.w);
+#endif
+}
+
+// Bilinear gather at plane term `fa` and lower corner (i1, i2) with
+// fractions (f1, f2); the same values as gather() (corners outside the
+// image read as zero), without branches: every corner is loaded, from
+// voxel 0 in place of one outside the image, and its value selected.
+__device__ __forceinline__ float gather_terms(const float *__restrict__ img, const AxisTerm &t1, const AxisTerm &t2,
+                                              int n1, int n2, int fa, int i1, int i2, float f1, float f2) {
+  const bool a0 = (unsigned)i1 < (unsigned)n1, a1 = (unsigned)(i1 + 1) < (unsigned)n1;
+  const bool b0 = (unsigned)i2 < (unsigned)n2, b1 = (unsigned)(i2 + 1) < (unsigned)n2;
+  const int j1 = max(i1, 0), j2 = max(i2, 0);
+  // from corner 0 to the next voxel along each axis (corner 0 at -1: the
+  // next one is voxel 0 itself)
+  const int d1 = (i1 < 0) ? 0 : (((j1 & t1.mask) == t1.mask) ? t1.wrap : t1.step);
+  const int d2 = (i2 < 0) ? 0 : (((j2 & t2.mask) == t2.mask) ? t2.wrap : t2.step);
+  const int base = fa + axis_index(t1, j1) + axis_index(t2, j2);
+  const float x0 = img[(a0 && b0) ? base : 0];
+  const float x1 = img[(a1 && b0) ? base + d1 : 0];
+  const float x2 = img[(a0 && b1) ? base + d2 : 0];
+  const float x3 = img[(a1 && b1) ? base + d1 + d2 : 0];
+  const float v0 = (a0 && b0) ? x0 : 0.0f, v1 = (a1 && b0) ? x1 : 0.0f;
+  const float v2 = (a0 && b1) ? x2 : 0.0f, v3 = (a1 && b1) ? x3 : 0.0f;
+  const float lo = fmaf(f1, v1 - v0, v0);
+  const float hi = fmaf(f1, v3 - v2, v2);
+  return fmaf(f2, hi - lo, lo);
 }
 
 // Kernels that scatter start their lanes at the brick boundary at or below
@@ -423,6 +492,91 @@ __host__ __device__ __forceinline__ bool decode_event(const GeomDev &g, const in
   id1 = c1 + g.n_cry * r1;
   id2 = c2 + g.n_cry * r2;
   return true;
+}
+
+
+// ---------------------------------------------------------------------------
+// The per-event forward walk of the projector kernels.
+
+// A ray as the lanes of a group of the forward walk read it: plane range,
+// axis and integer parts, the TOF coefficients and plane length, and the
+// interpolation coordinates in double.  In float32, F + j V of a plane a
+// few hundred planes from the first carries an error of up to 3e-5 voxel
+// (one unit in the last place near 300), which a LOR that grazes an edge of
+// the activity turns into a relative error of that order; the forward
+// projector is bound by its memory instructions, not by its arithmetic, so
+// its coordinates take double precision.
+struct RayPack {
+  int4 p;     // {m0, nplanes, a, I1}
+  int4 q;     // {I2, bits of A, B, L}
+  double2 u1; // {F1, V1}
+  double2 u2; // {F2, V2}
+};
+
+// One sample of the forward walk: {weight, interpolated value} at plane
+// offset j (weight 0 for j < 0), plane term fa.
+template <bool TOF>
+__device__ __forceinline__ float2 fwd_sample(const GeomDev &g, const float *__restrict__ x, const AxisTerm &t1,
+                                            const AxisTerm &t2, int n1, int n2, const RayPack &pk, float A, float B,
+                                            float D, int j, int fa) {
+  const double u1 = fma((double)j, pk.u1.y, pk.u1.x), u2 = fma((double)j, pk.u2.y, pk.u2.x);
+  const double fl1 = floor(u1), fl2 = floor(u2);
+  // the loads first: the TOF weight's arithmetic then runs while they are
+  // in flight
+  const float v = gather_terms(x, t1, t2, n1, n2, fa, pk.p.w + (int)fl1, pk.q.x + (int)fl2, (float)(u1 - fl1),
+                               (float)(u2 - fl2));
+  float w = 1.0f;
+  if constexpr (TOF) {
+    const float vh = fmaf(-(float)j, B, A);
+    w = tof_weight(vh, vh - D, g.vclip, g.inv_norm);
+  }
+  return make_float2((j >= 0) ? w : 0.0f, v);
+}
+
+// The planes of one event for lane gl of its group: m0 + j for j = gl -
+// (brick offset of m0), + 8, ...  Returns the lane's weighted sum.
+template <bool TOF>
+__device__ __forceinline__ float fwd_walk(const GeomDev &g, const float *__restrict__ x, const RayPack &pk,
+                                          float D, int gl) {
+  const int np = pk.p.y, m0 = pk.p.x, a = pk.p.z;
+  const float A = __int_as_float(pk.q.y), B = __int_as_float(pk.q.z);
+  const int b1 = (a == 0) ? 1 : 0, b2 = (a == 2) ? 1 : 2;
+  const AxisTerm ta = axis_term(g.lay, a), t1 = axis_term(g.lay, b1), t2 = axis_term(g.lay, b2);
+  const int n1 = sel3(b1, g.n[0], g.n[1], g.n[2]), n2 = sel3(b2, g.n[0], g.n[1], g.n[2]);
+  int j = gl - (m0 & ta.mask & kMaxBrickOffset);
+  // plane term of m0 + j (>= 0: the offset stays inside m0's brick),
+  // advanced by whole bricks, 8 planes at a time
+  int fa = axis_index(ta, m0 + j);
+  const int fa_step = (8 >> ta.s) * ta.bs;
+  float acc = 0.0f;
+  for (; j < np; j += 8, fa += fa_step) {
+    const float2 s = fwd_sample<TOF>(g, x, t1, t2, n1, n2, pk, A, B, D, j, fa);
+    acc = fmaf(s.x, s.y, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ RayPack pack_ray(const Ray &r) {
+  RayPack pk;
+  pk.p = make_int4(r.m0, r.nplanes, r.a, r.I1);
+  pk.q = make_int4(r.I2, __float_as_int(r.A), __float_as_int(r.B), __float_as_int(r.L));
+  pk.u1 = make_double2(r.F1d, r.V1d);
+  pk.u2 = make_double2(r.F2d, r.V2d);
+  return pk;
+}
+
+__device__ __forceinline__ RayPack empty_ray() {
+  RayPack pk;
+  pk.p = make_int4(0, 0, 0, 0);
+  pk.q = make_int4(0, 0, 0, 0);
+  pk.u1 = make_double2(0.0, 0.0);
+  pk.u2 = make_double2(0.0, 0.0);
+  return pk;
+}
+
+// D of a single TOF bin as setup_ray computes it.
+__host__ __device__ __forceinline__ float tof_bin_width(const GeomDev &g) {
+  return (float)(2.0 * (0.5 * g.tof_bin) * g.inv_sr2);
 }
 
 }  // namespace lmk

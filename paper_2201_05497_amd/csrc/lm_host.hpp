@@ -98,6 +98,22 @@ int launch_sens_lines(const GeomDev &g, const int *cyl, float *img, hipStream_t 
 // temporaries of the sort do not fit.
 int launch_back_lines(const GeomDev &g, const int *cyl, const float *v, const int16_t *ev, long long n, float *img,
                       hipStream_t st, bool &queued);
+// For a long list (at least 64 events per transaxial crystal pair): the
+// events' indices in the order of a counting sort by transaxial crystal
+// pair (any scanner), in a stream-ordered allocation *order (nullptr: the
+// list is short or the temporaries do not fit), and, when offsets is not
+// NULL, the first sorted position of every pair and of the last bucket
+// (events of one crystal or out of range) plus the list's end, nlines + 2
+// entries; the caller frees both stream-ordered.
+int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsigned **order, unsigned **offsets,
+                        hipStream_t st);
+// Forward projection of a sorted list by line (lm_lines.hip): queued is set
+// when the kernel was launched (a scanner with at least two rings and two
+// crystals, and an LDS sheet of the image's planes that fits one block);
+// it writes every out[e] when *cyl is set at run time and nothing
+// otherwise.  x in the brick layout of g.
+int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int16_t *ev, const unsigned *order,
+                     const unsigned *off, long long n, float *out, hipStream_t st, bool &queued);
 // Plan-internal event records: int4 {id1, id2, k, s bits}.
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
                    hipStream_t st);

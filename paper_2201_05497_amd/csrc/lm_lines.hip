@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int *cyl, co
 __global__ __launch_bounds__(1024) void k_line_offsets(const int *cyl, const unsigned *cnt, long long n,
                                                        unsigned *off) {
   __shared__ unsigned part[1024];
-  if (!*cyl) return;
+  if (cyl && !*cyl) return;
   const int t = threadIdx.x;
   const long long seg = (n + 1023) / 1024;
   const long long a = min(n, t * seg), b = min(n, a + seg);
@@ -551,6 +551,241 @@ __global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const int *cyl, co
   }
 }
 
+// The order of lm_fwd for a long list: bucket of every event (its
+// transaxial crystal pair c1 != c2 as line index; events of one crystal or
+// out of range in bucket nlines) and its rank there, then the events'
+// indices placed by bucket.
+__global__ __launch_bounds__(256) void k_fwd_keys(GeomDev g, const int16_t *ev, long long n, long long nlines,
+                                                  unsigned *key, unsigned *rank, unsigned *cnt) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int c1 = ev[5 * e], c2 = ev[5 * e + 2];
+  long long L = nlines;
+  if ((unsigned)c1 < (unsigned)g.n_cry && (unsigned)c2 < (unsigned)g.n_cry && c1 != c2) {
+    const long long lo = min(c1, c2), hi = max(c1, c2), nc = g.n_cry;
+    L = lo * nc - lo * (lo + 1) / 2 + (hi - lo - 1);
+  }
+  key[e] = (unsigned)L;
+  rank[e] = atomicAdd(cnt + L, 1u);
+}
+
+__global__ __launch_bounds__(256) void k_fwd_place(const unsigned *key, const unsigned *rank, const unsigned *off,
+                                                   long long n, unsigned *order) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  order[off[key[e]] + rank[e]] = (unsigned)e;
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection of a long event list by line.  After the counting
+// sort by transaxial crystal pair, one block takes the events of one line:
+// it first interpolates the image across the line transaxially, plane by
+// plane, into an LDS sheet s[m][z] = (1 - f1(m)) x(m, i1(m), z) + f1(m)
+// x(m, i1(m) + 1, z) over the planes m the line crosses; the bilinear
+// sample of any LOR of the line at plane m is then (1 - f2) s[m][k0] +
+// f2 s[m][k0 + 1] with the LOR's own z coordinate k0 + f2, the same
+// interpolation as the per-event projector (across the transaxial axis
+// first, then along z).  Groups of 8 lanes walk the planes of one event
+// each, so the image is read once per line instead of once per event.
+// Events whose dominant axis is z (and, in extra blocks, the bucket of
+// events of one crystal or out of range) take the per-event walk.
+
+constexpr int kFwdLineBlock = 1024;                   // 16 wavefronts
+constexpr int kFwdLineGroups = kFwdLineBlock / 8;     // events walked at once
+constexpr int kFwdTailBlocks = 256;                   // blocks of the last bucket
+
+// Transaxial geometry of a line in its orientation c1 < c2 (ring 0 crystals):
+// planes m of the dominant transaxial axis a, LOR parameter lam(m) = lam0 + m
+// dlam (0 at c1, 1 at c2), the other transaxial coordinate u1(m) = (p1b +
+// lam db - c0b) / hb in voxels; planes [mlo, mlo + nm) have lam in [0, 1].
+struct FwdLine {
+  int a, nb, mlo, nm;
+  double lam0, dlam, p1b, db, c0b, hb;
+  double dxy2, ha_over_da;
+};
+
+__host__ __device__ __forceinline__ FwdLine fwd_line(const GeomDev &g, int c1, int c2) {
+  FwdLine q;
+  const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
+  q.a = dominant_axis(d2[0] - d1[0], d2[1] - d1[1], 0.0f);
+  const int b = 1 - q.a;
+  const double p1a = q.a ? d1[1] : d1[0], da = q.a ? (double)d2[1] - d1[1] : (double)d2[0] - d1[0];
+  q.p1b = b ? d1[1] : d1[0];
+  q.db = b ? (double)d2[1] - d1[1] : (double)d2[0] - d1[0];
+  const double dx = (double)d2[0] - d1[0], dy = (double)d2[1] - d1[1];
+  q.dxy2 = dx * dx + dy * dy;
+  const double ha = g.h[q.a], c0a = g.c0[q.a];
+  q.c0b = g.c0[b];
+  q.hb = g.h[b];
+  q.nb = g.n[b];
+  q.ha_over_da = ha / fabs(da);
+  q.lam0 = (c0a - p1a) / da;
+  q.dlam = ha / da;
+  const double m_at0 = -q.lam0 / q.dlam, m_at1 = (1.0 - q.lam0) / q.dlam;
+  const double lo = fmax(0.0, ceil(fmin(m_at0, m_at1))), hi = fmin((double)(g.n[q.a] - 1), floor(fmax(m_at0, m_at1)));
+  q.mlo = (int)lo;
+  q.nm = hi >= lo ? (int)(hi - lo) + 1 : 0;
+  return q;
+}
+
+// The rows of the sheet are padded by one float so that the 8 lanes of a
+// group, on 8 consecutive planes, read 8 different LDS banks.
+__host__ __device__ __forceinline__ int sheet_row(int nz) { return nz + 1; }
+
+size_t fwd_sheet_bytes(const GeomDev &g) {
+  const size_t nm = (size_t)std::max(g.n[0], g.n[1]);
+  return (nm * sheet_row(g.n[2]) + 2 * nm) * sizeof(float);
+}
+
+template <bool TOF>
+__host__ __device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &q, const float *S, int nz, double A,
+                                               double B, double az, double bz, int m0, int m1, float D, int gl) {
+  const int row = sheet_row(nz);
+  float acc = 0.0f;
+  for (int m = m0 + gl; m <= m1; m += 8) {
+    const double lam = fma((double)m, q.dlam, q.lam0);
+    float w = 1.0f;
+    if constexpr (TOF) {
+      const float vh = (float)fma(-lam, B, A);
+      w = tof_weight(vh, vh - D, g.vclip, g.inv_norm);
+    }
+    const double u2 = fma(lam, bz, az);
+    const double fl = floor(u2);
+    const int k0 = (int)fl;
+    const float f2 = (float)(u2 - fl);
+    const float *sr = S + (m - q.mlo) * row;
+    const bool ok0 = (unsigned)k0 < (unsigned)nz, ok1 = (unsigned)(k0 + 1) < (unsigned)nz;
+    const float t0 = sr[ok0 ? k0 : 0], t1 = sr[ok1 ? k0 + 1 : 0];
+    const float s0 = ok0 ? t0 : 0.0f, s1 = ok1 ? t1 : 0.0f;
+    acc = fmaf(w, fmaf(f2, s1 - s0, s0), acc);
+  }
+  return acc;
+}
+
+// Per-event projection of event e by a group (the per-event projector's
+// walk over the image x); 0 for an invalid event.
+__device__ __forceinline__ float fwd_event(const GeomDev &g, const float *__restrict__ x, const int16_t *ev, float D,
+                                           int gl) {
+  int id1, id2, k;
+  if (!decode_event(g, ev, id1, id2, k)) return 0.0f;
+  const RayPack pk = pack_ray(setup_ray(g, id1, id2, k, W_BIN, 1 << 20));
+  if (pk.p.y <= 0) return 0.0f;
+  const float acc = g.tof_on ? fwd_walk<true>(g, x, pk, D, gl) : fwd_walk<false>(g, x, pk, D, gl);
+  return __int_as_float(pk.q.w) * acc;
+}
+
+// Blocks b < 8 ceil(nlines / 8): the events of one line each, sorted
+// positions off[L] .. off[L + 1] with L = (b % 8) ceil(nlines / 8) + b / 8
+// (blocks are dealt to the XCDs round robin, so consecutive lines, which
+// read nearby voxels, share an XCD's L2; blocks with L >= nlines do
+// nothing); the kFwdTailBlocks blocks after them: the last bucket (events
+// of one crystal, or out of range) by the per-event walk.  Does nothing
+// unless *cyl is set.
+__global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const int *cyl, const float *__restrict__ x,
+                                                             const int16_t *__restrict__ ev, const unsigned *order,
+                                                             const unsigned *off, long long nlines,
+                                                             float *__restrict__ out) {
+  extern __shared__ float sh[];
+  if (!*cyl) return;
+  const int tid = threadIdx.x, grp = tid >> 3, gl = tid & 7;
+  const float D = tof_bin_width(g);
+  const long long per = (nlines + 7) / 8;
+  long long blk = blockIdx.x;
+  if (blk >= 8 * per) {  // the last bucket
+    const unsigned t0 = off[nlines], t1 = off[nlines + 1];
+    for (unsigned pos = t0 + (unsigned)((blk - 8 * per) * kFwdLineGroups + grp); pos < t1;
+         pos += kFwdTailBlocks * kFwdLineGroups) {
+      const unsigned e = order[pos];
+      float acc = fwd_event(g, x, ev + 5 * (size_t)e, D, gl);
+      acc = group_sum<8>(acc);
+      if (gl == 0) out[e] = acc;
+    }
+    return;
+  }
+  blk = (blk % 8) * per + blk / 8;
+  if (blk >= nlines) return;
+  const unsigned e0 = off[blk], e1 = off[blk + 1];
+  if (e0 == e1) return;
+  int c1, c2;
+  pair_of(blk, g.n_cry, c1, c2);
+  const FwdLine q = fwd_line(g, c1, c2);
+  const int nz = g.n[2], row = sheet_row(nz);
+  const int nm_max = max(g.n[0], g.n[1]);
+  float *S = sh;
+  int *pi1 = (int *)(sh + (size_t)nm_max * row);
+  float *pf1 = sh + (size_t)nm_max * row + nm_max;
+  for (int mm = tid; mm < q.nm; mm += kFwdLineBlock) {
+    const double lam = fma((double)(q.mlo + mm), q.dlam, q.lam0);
+    const double u1 = (q.p1b + lam * q.db - q.c0b) / q.hb;
+    const double fl = floor(u1);
+    // planes whose corners both lie outside the image read nothing
+    pi1[mm] = (fl < -1.0 || fl > (double)q.nb - 1.0) ? -2 : (int)fl;
+    pf1[mm] = (float)(u1 - fl);
+  }
+  __syncthreads();
+  for (int t = tid; t < q.nm * nz; t += kFwdLineBlock) {
+    const int mm = t % q.nm, k = t / q.nm;  // planes fastest: along the dominant axis
+    const int m = q.mlo + mm, i1 = pi1[mm];
+    const float f1 = pf1[mm];
+    float x0 = 0.0f, x1 = 0.0f;
+    if ((unsigned)i1 < (unsigned)q.nb) x0 = x[q.a == 0 ? vidx(g.lay, m, i1, k) : vidx(g.lay, i1, m, k)];
+    if ((unsigned)(i1 + 1) < (unsigned)q.nb)
+      x1 = x[q.a == 0 ? vidx(g.lay, m, i1 + 1, k) : vidx(g.lay, i1 + 1, m, k)];
+    S[mm * row + k] = fmaf(f1, x1 - x0, x0);
+  }
+  __syncthreads();
+  const double ihz = 1.0 / g.h[2];
+  for (unsigned pos = e0 + grp; pos < e1; pos += kFwdLineGroups) {
+    const unsigned e = order[pos];
+    const int16_t *r = ev + 5 * (size_t)e;
+    int id1, id2, k;
+    float val = 0.0f;
+    if (decode_event(g, r, id1, id2, k)) {
+      int r1 = r[1], r2 = r[3];
+      if (r[0] > r[2]) {  // the line's orientation: swap the ends, mirror the TOF bin
+        const int t = r1;
+        r1 = r2;
+        r2 = t;
+        k = -k;
+      }
+      const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
+      const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
+      if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], z2f - z1f) == 2) {
+        float acc = fwd_event(g, x, r, D, gl);
+        val = group_sum<8>(acc);
+      } else {
+        const double dz = (double)z2f - z1f;
+        const double dn = sqrt(q.dxy2 + dz * dz);
+        // vh(lam) = A - lam B (units of sigma sqrt 2), z(lam) = az + lam bz (voxels)
+        const double A = (k * g.tof_bin + 0.5 * g.tof_bin + 0.5 * dn) * g.inv_sr2, B = dn * g.inv_sr2;
+        const double az = ((double)z1f - g.c0[2]) * ihz, bz = dz * ihz;
+        double lo = q.mlo, hi = q.mlo + q.nm - 1;
+        if (g.tof_on) {  // vh in [-vclip, vclip + D], one plane of margin
+          const double ma = ((A - ((double)g.vclip + D)) / B - q.lam0) / q.dlam;
+          const double mb = ((A + (double)g.vclip) / B - q.lam0) / q.dlam;
+          lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
+          hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
+        }
+        if (bz != 0.0) {  // z in (-1, nz), one plane of margin
+          const double ma = ((-1.0 - az) / bz - q.lam0) / q.dlam, mb = (((double)nz - az) / bz - q.lam0) / q.dlam;
+          lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
+          hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
+        } else if (az <= -1.0 || az >= (double)nz) {
+          hi = lo - 1.0;
+        }
+        float acc = 0.0f;
+        if (hi >= lo) {
+          acc = g.tof_on ? fwd_line_walk<true>(g, q, S, nz, A, B, az, bz, (int)lo, (int)hi, D, gl)
+                         : fwd_line_walk<false>(g, q, S, nz, A, B, az, bz, (int)lo, (int)hi, D, gl);
+        }
+        acc = group_sum<8>(acc);
+        val = (float)(q.ha_over_da * dn) * acc;
+      }
+    }
+    if (gl == 0) out[e] = val;
+  }
+}
+
 // The scanner is cylindrical when crystal c of ring r sits at (x_c, y_c, z_r):
 // the same transaxial position in every ring and one z per ring, with z_r
 // increasing in r.  One block checks every crystal and writes flag[0] = 1
@@ -608,6 +843,66 @@ int launch_sens_lines(const GeomDev &g, const int *cyl, float *img, hipStream_t 
   return LM_OK;
 }
 
+
+int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsigned **order, unsigned **offsets,
+                        hipStream_t st) {
+  *order = nullptr;
+  if (offsets) *offsets = nullptr;
+  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
+  if (g.n_cry < 2 || n < 64 * nlines || n >= (1LL << 32) || nlines >= (1LL << 31)) return LM_OK;
+  unsigned *key = nullptr, *rank = nullptr, *cnt = nullptr, *off = nullptr, *ord = nullptr;
+  auto release = [&](bool keep) {  // release errors are not reported
+    for (unsigned *q : {key, rank, cnt})
+      if (q) (void)hipFreeAsync(q, st);
+    if (ord && !keep) (void)hipFreeAsync(ord, st);
+    if (off && !(keep && offsets)) (void)hipFreeAsync(off, st);
+  };
+  hipError_t e = hipMallocAsync((void **)&key, n * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&rank, n * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, (nlines + 1) * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&off, (nlines + 2) * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&ord, n * sizeof(unsigned), st);
+  if (e == hipErrorOutOfMemory) {
+    release(false);
+    (void)hipGetLastError();
+    return LM_OK;  // the list is projected in its own order
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, (nlines + 1) * sizeof(unsigned), st);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fwd_keys, dim3(grid), dim3(256), 0, st, g, ev, n, nlines, key, rank, cnt);
+    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, nullptr, cnt, nlines + 1, off);
+    hipLaunchKernelGGL(k_fwd_place, dim3(grid), dim3(256), 0, st, key, rank, off, n, ord);
+    e = hipGetLastError();
+  }
+  release(e == hipSuccess);
+  LM_TRY_HIP(e);
+  *order = ord;
+  if (offsets) *offsets = off;
+  return LM_OK;
+}
+
+int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int16_t *ev, const unsigned *order,
+                     const unsigned *off, long long n, float *out, hipStream_t st, bool &queued) {
+  queued = false;
+  if (!lines_possible(g) || n == 0) return LM_OK;
+  static int lds_max = -1;  // the largest LDS allocation of a block (device 0's)
+  if (lds_max < 0) {
+    int dev = 0, v = 0;
+    LM_TRY_HIP(hipGetDevice(&dev));
+    LM_TRY_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    lds_max = v;
+  }
+  const size_t bytes = fwd_sheet_bytes(g);
+  if (bytes > (size_t)lds_max) return LM_OK;
+  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
+  const long long nb = 8 * ((nlines + 7) / 8) + kFwdTailBlocks;
+  hipLaunchKernelGGL(k_fwd_lines, dim3((unsigned)nb), dim3(kFwdLineBlock), bytes, st, g, cyl, x, ev, order, off,
+                     nlines, out);
+  LM_TRY_HIP(hipGetLastError());
+  queued = true;
+  return LM_OK;
+}
 
 // Back projection of a long list by line: worth it when the lines carry
 // many events each (the per-block flush costs about as many atomics as

@@ -24,15 +24,22 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Event sources: the caller's int16[5] records, or the plan's int4 records.
+// Event sources: the caller's int16[5] records, the plan's int4 records,
+// or the caller's records in a given order (out[order[e]] for the e-th).
+// kXcdOrder: the blocks of a launch take the list in eight contiguous
+// parts, one per XCD (blocks are dealt to the XCDs round robin), so that
+// the events of a part share that XCD's L2.
 struct CallerEvents {
+  static constexpr bool kXcdOrder = false;
   const int16_t *ev;
   CallerEvents offset(long long o) const { return CallerEvents{ev + 5 * o}; }
   __device__ __forceinline__ bool get(const GeomDev &g, long long e, int &id1, int &id2, int &k) const {
     return decode_event(g, ev + 5 * e, id1, id2, k);
   }
+  __device__ __forceinline__ long long slot(long long e) const { return e; }
 };
 struct PlanEvents {
+  static constexpr bool kXcdOrder = false;
   const int4 *rec;
   PlanEvents offset(long long o) const { return PlanEvents{rec + o}; }
   __device__ __forceinline__ bool get(const GeomDev &, long long e, int &id1, int &id2, int &k) const {
@@ -42,29 +49,74 @@ struct PlanEvents {
     k = r.z;
     return true;
   }
+  __device__ __forceinline__ long long slot(long long e) const { return e; }
+};
+struct SortedEvents {
+  static constexpr bool kXcdOrder = true;
+  const int16_t *ev;
+  const unsigned *order;
+  SortedEvents offset(long long o) const { return SortedEvents{ev, order + o}; }
+  __device__ __forceinline__ bool get(const GeomDev &g, long long e, int &id1, int &id2, int &k) const {
+    return decode_event(g, ev + 5 * (long long)order[e], id1, id2, k);
+  }
+  __device__ __forceinline__ long long slot(long long e) const { return order[e]; }
 };
 
-template <int LPE, class Src>
-__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, const float *__restrict__ x, Src src,
+// Lanes per event of the forward projector, and events per launch (2^19
+// blocks).
+constexpr int kFwdLanes = 8;
+constexpr long long kFwdLaunch = 1LL << 27;
+
+// Forward projection.  A wavefront takes 64 consecutive events of the
+// source: lane e first sets up the ray of event e (the double-precision
+// set-up runs once per event rather than once per lane of a group) and
+// stores it in LDS; then, in eight rounds, each group of kFwdLanes = 8 lanes
+// walks the planes of one event (lane l of the group from the brick
+// boundary at or below the first plane, every 8th plane), and lane e of the
+// wavefront collects event e's sum for one store per lane.
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, const int *skip, const float *__restrict__ x, Src src,
                                                 long long n, float *__restrict__ out) {
-  const int lane = threadIdx.x % LPE;
-  const long long e = (long long)blockIdx.x * (kBlock / LPE) + threadIdx.x / LPE;
-  if (e >= n) return;
-  int id1 = 0, id2 = 0, k = 0;
-  float acc = 0.0f, L = 0.0f;
-  if (src.get(g, e, id1, id2, k)) {
-    const Ray r = setup_ray(g, id1, id2, k, W_BIN, 1 << 20);
-    L = r.L;
-    // lanes start at the brick boundary at or below the first plane, so
-    // that the LPE planes of one gather span as few bricks as possible
-    for (int j = lane - brick_offset(g.lay, r); j < r.nplanes; j += LPE) {
-      if (j < 0) continue;
-      const Sample s = sample_at(g, r, j, g.tof_on);
-      acc = fmaf(s.w, gather(g, x, r, s), acc);
-    }
+  static_assert(kFwdLanes == 8, "eight groups of eight lanes per wavefront");
+  __shared__ RayPack rays[kBlock];
+  if (skip && *skip) return;  // the list went to the path by line
+  const int lane = threadIdx.x & 63;
+  const int wbase = threadIdx.x & ~63;
+  long long blk = blockIdx.x;
+  if constexpr (Src::kXcdOrder) {  // gridDim.x is a multiple of 8
+    const long long per = gridDim.x / 8;
+    blk = (blk % 8) * per + blk / 8;
   }
-  acc = group_sum<LPE>(acc);
-  if (lane == 0) out[e] = L * acc;
+  if (blk * kBlock + wbase >= n) return;  // the whole wavefront is past the end
+  const long long e = blk * kBlock + threadIdx.x;
+  {
+    // every field defined on every path: lanes past the end and invalid
+    // events store an empty ray, and only valid events reach the set-up
+    // (which reads the crystal table at the decoded ids)
+    RayPack pk = empty_ray();
+    int id1 = 0, id2 = 0, k = 0;
+    if (e < n && src.get(g, e, id1, id2, k)) pk = pack_ray(setup_ray(g, id1, id2, k, W_BIN, 1 << 20));
+    rays[threadIdx.x] = pk;
+  }
+  // LDS operations of one wavefront complete in order; the fences keep the
+  // compiler from moving the reads above the writes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float D = tof_bin_width(g);
+  const int gl = lane & 7, grp = lane >> 3;
+  float mine = 0.0f, L = 0.0f;
+  for (int round = 0; round < 8; ++round) {
+    const RayPack pk = rays[wbase + 8 * round + grp];
+    float acc = 0.0f;
+    if (pk.p.y > 0) acc = g.tof_on ? fwd_walk<true>(g, x, pk, D, gl) : fwd_walk<false>(g, x, pk, D, gl);
+    acc = group_sum<8>(acc);
+    // lanes 8 round .. 8 round + 7 take the sums of groups 0 .. 7
+    const float got = __shfl(acc, 8 * gl);
+    if (grp == round) mine = got;
+  }
+  L = __int_as_float(rays[threadIdx.x].q.w);
+  if (e < n) out[src.slot(e)] = L * mine;
 }
 
 // Per-wavefront LDS staging of the interleaved scatter (4 wavefronts per
@@ -271,22 +323,17 @@ int max_planes(const lmk::GeomDev &g, int mode) {
 
 namespace lmk {
 
-// Lanes per event of the forward projector.  A lane group shares one
-// event's double-precision set-up, which the whole wavefront executes once
-// for its 64 / kFwdLanes events, so small groups amortise it; measured on
-// the 3D scanner, 8 lanes are 1.9x faster than 64 (0.44 against 1.22 ms per
-// 1e6 events on 200x200x96, 0.68 against 1.32 on 300x300x96) although the
-// groups of a wavefront then wait for its longest event.
-constexpr int kFwdLanes = 8;
-
 template <class Src>
-static int fwd_impl(const GeomDev &g, const float *x, Src src, long long n, float *out, hipStream_t st) {
+static int fwd_impl(const GeomDev &g, const float *x, Src src, long long n, float *out, hipStream_t st,
+                    const int *skip = nullptr) {
   if (n == 0) return LM_OK;
-  constexpr int L = kFwdLanes;
-  for (long long o = 0; o < n; o += chunk_items(L)) {
-    const long long m = std::min(chunk_items(L), n - o);
-    hipLaunchKernelGGL((k_fwd<L, Src>), dim3(blocks_for(m, L)), dim3(kBlock), 0, st, g, x, src.offset(o), m,
-                       out + o);
+  for (long long o = 0; o < n; o += kFwdLaunch) {
+    const long long m = std::min(kFwdLaunch, n - o);
+    unsigned nb = blocks_for(m, 1);
+    if (Src::kXcdOrder) nb = (nb + 7) / 8 * 8;
+    // sorted sources write out[order[e]]: out is the whole list's
+    hipLaunchKernelGGL((k_fwd<Src>), dim3(nb), dim3(kBlock), 0, st, g, skip, x, src.offset(o), m,
+                       Src::kXcdOrder ? out : out + o);
     LM_TRY_HIP(hipGetLastError());
   }
   return LM_OK;
@@ -448,7 +495,26 @@ int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float
   lmh::BrickImage b;
   if (int rc = b.alloc(g, st)) return rc;
   if (int rc = lmk::launch_to_layout(g.n, g.lay, 1, x, b.p, st)) return rc;
-  return launch_fwd(g, b.p, ev, n, out, st);
+  // a long list is sorted by transaxial crystal pair and projected line by
+  // line on a cylindrical scanner, else per event in the sorted order (so
+  // that the events of a line share cache lines)
+  unsigned *order = nullptr, *off = nullptr;
+  if (int rc = lmk::sort_events_by_line(g, ev, n, &order, &off, st)) return rc;
+  if (!order) return launch_fwd(g, b.p, ev, n, out, st);
+  int rc = LM_OK;
+  {
+    DevFlag cyl;
+    bool queued = false;
+    if (lines_possible(g)) {
+      rc = cyl.alloc(st);
+      if (rc == LM_OK) rc = launch_cylindrical(g, cyl.p, st);
+      if (rc == LM_OK) rc = launch_fwd_lines(g, cyl.p, b.p, ev, order, off, n, out, st, queued);
+    }
+    if (rc == LM_OK) rc = fwd_impl(g, b.p, SortedEvents{ev, order}, n, out, st, queued ? cyl.p : nullptr);
+  }
+  (void)hipFreeAsync(order, st);  // release errors have no caller to go to
+  (void)hipFreeAsync(off, st);
+  return rc;
 }
 
 int lm_fwd_noalloc(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out, void *stream) {

@@ -2,6 +2,8 @@
 FP64 oracle, through the C ABI.  Tolerances: projections per event
 |gpu - orc| <= 1e-5 max(|orc|, 1e-3 mean|orc|); back projections
 ||gpu - orc||_inf <= 1e-4 ||orc||_inf."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -10,6 +12,7 @@ import lmsynth
 import oracle
 from tests.helpers import img_err, problem_2d, problem_3d, proj_err, report, smooth_image
 from tests.test_oracle_projector import all_bins
+from paper_2201_05497_amd import _lib
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +154,16 @@ def test_edge_cases(P):
     # degenerate LOR (same crystal twice)
     same = np.array([[5, 0, 5, 0, 0]], dtype=np.int16)
     assert float(P.lm_fwd(Gg, x, Gg.events(same))[0]) == 0.0
+    # indices far out of range (their crystal-table rows would lie far past
+    # its end) among valid events, in a list that ends inside a wavefront:
+    # value 0, the valid events unchanged
+    far = np.array([[32767, 32767, 0, 0, 0], [0, 0, 32767, 32767, 0], [-32768, -32768, 5, 0, 0],
+                    [7, 0, 180, 32767, 0]], dtype=np.int16)
+    mixed = np.concatenate([p.events[:100], far, p.events[100:157]])
+    out = P.lm_fwd(Gg, x, Gg.events(mixed)).cpu().numpy()
+    ref = P.lm_fwd(Gg, x, Gg.events(np.concatenate([p.events[:100], p.events[100:157]]))).cpu().numpy()
+    assert np.all(out[100:104] == 0.0)
+    assert np.array_equal(np.concatenate([out[:100], out[104:]]), ref)
 
 
 def test_sens_2d_and_3d(P):
@@ -211,6 +224,42 @@ def test_back_by_line_matches_oracle(P, tof):
     _back_check(P, Gg, Go, v[:8000], ev[:8000], f"3d back per event tof={tof}")
 
 
+def test_fwd_by_line_order_matches_oracle(P):
+    """A list with at least 64 events per transaxial crystal pair (here 150
+    on each of the 276 pairs of a 24-crystal, 36-ring scanner) is sorted by
+    pair and projected line by line (an LDS sheet of the image interpolated
+    across each line, the per-event walk for LORs whose dominant axis is z
+    and for the bucket of events of one crystal or out of range); every
+    event's value lands in its own slot.  Included: events whose dominant
+    axis is z, the same crystal twice, out-of-range crystals, rings and TOF
+    bins (value 0), and LORs that miss the image."""
+    p = lmsynth.tiny_3d(n_cry=24, n_ring=36, nxy=12, nz=36, h=2.6, radius=30.0, pitch=2.6, n_tof=9,
+                        tof_bin=12.0, fwhm=30.0)
+    ev = lmsynth.random_events(p, 41400, seed=35, min_sep=1)
+    rng = np.random.default_rng(36)
+    axial = np.stack([np.full(200, 5), rng.integers(0, 36, 200), np.full(200, 5), rng.integers(0, 36, 200),
+                      rng.integers(-4, 5, 200)], axis=1).astype(np.int16)
+    odd = np.array([[3, 0, 3, 0, 0], [24, 0, 3, 0, 0], [3, 36, 7, 0, 0], [3, 0, 7, 0, 5], [-1, 0, 7, 0, 0],
+                    [0, 0, 1, 35, 0]], dtype=np.int16)
+    ev = np.concatenate([ev[:20000], axial, odd, ev[20000:]])
+    assert len(ev) >= 64 * (24 * 23 // 2)
+    Gg, Go = _pair(P, p)
+    x = smooth_image(Go.shape, 37)
+    xt = torch.as_tensor(x, device="cuda")
+    got = P.lm_fwd(Gg, xt, Gg.events(ev)).cpu().numpy()
+    bad = np.arange(20201, 20205)  # out of range: value 0, no oracle counterpart
+    assert np.all(got[bad] == 0.0) and got[20200] == 0.0
+    ok = np.setdiff1d(np.arange(len(ev)), bad)
+    emax, emean = proj_err(got[ok], oracle.fwd(Go, x, ev[ok]))
+    report("3d fwd by line order", events=len(ev), max_err=emax, mean_err=emean)
+    assert emax <= PROJ_TOL
+    # below the threshold the list is projected per event in its own order
+    got_short = P.lm_fwd(Gg, xt, Gg.events(ev[:8000])).cpu().numpy()
+    emax, _ = proj_err(got_short, got[:8000].astype(np.float64))
+    report("3d fwd per event against by line", events=8000, max_err=emax)
+    assert emax <= PROJ_TOL
+
+
 def test_non_cylindrical_scanner_takes_per_lor_paths(P):
     """A crystal table that is not cylindrical (one crystal of one ring
     moved by 0.05 mm) makes lm_sens and a long lm_back take the per-LOR
@@ -241,13 +290,17 @@ def test_large_image_planes_bound(P):
 
 
 def test_chunked_launches(P):
-    """Inputs larger than one launch (2^22 blocks): on a list of two lm_fwd
-    launches (32 events per block) and sixteen per-event lm_back launches (4
-    events per block) plus a ragged tail, the events around every launch
-    boundary match the oracle in projection, and in back projection with
-    values that are zero except around the boundaries.  One crystal of the
-    table is moved by 0.05 mm, so that lm_back takes its per-event kernel
-    and not the path by transaxial line."""
+    """Inputs larger than one launch (2^22 blocks): on a list of two
+    forward launches (32 events per block) and sixteen per-event lm_back
+    launches (4 events per block) plus a ragged tail, the events around
+    every launch boundary match the oracle in projection, and in back
+    projection with values that are zero except around the boundaries.
+    The list's own order is projected by lm_fwd_noalloc (which never sorts);
+    lm_fwd, which takes the list in the order of the sort by crystal pair
+    (launch boundaries at other events), gives every event the same value
+    bit for bit.  One crystal of the table is moved by 0.05 mm, so that
+    lm_back takes its per-event kernel and not the path by transaxial
+    line."""
     p = problem_3d(1_000_000)
     sc, tof = p.scanner, p.tof
     det = p.det.copy()
@@ -263,12 +316,19 @@ def test_chunked_launches(P):
     def around(step):
         return np.concatenate([np.arange(c - 50, c + 50) for c in range(step, n, step)] + [np.arange(n - 50, n)])
 
-    out = P.lm_fwd(Gg, torch.as_tensor(x, device="cuda"), evt)
+    xt = torch.as_tensor(x, device="cuda")
+    out = torch.full((n,), float("nan"), device="cuda")
+    _lib.check(_lib.load().lm_fwd_noalloc(ctypes.byref(Gg._c), xt.data_ptr(), evt.data_ptr(), n, out.data_ptr(),
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "lm_fwd_noalloc")
     idx = around(fwd_launch)
     emax, _ = proj_err(out[torch.as_tensor(idx, device="cuda")].cpu().numpy(), oracle.fwd(Go, x, ev[idx]))
-    del out
-    report("chunk boundaries fwd", events=n, max_err=emax)
+    sorted_out = P.lm_fwd(Gg, xt, evt)
+    same = bool(torch.equal(sorted_out, out))
+    del out, sorted_out
+    report("chunk boundaries fwd", events=n, max_err=emax, sorted_order_identical=int(same))
     assert emax <= PROJ_TOL
+    assert same
     jdx = around(back_launch)
     vals = np.random.default_rng(15).uniform(0.1, 1, len(jdx)).astype(np.float32)
     v = torch.zeros(n, device="cuda")
