@@ -303,6 +303,82 @@ __host__ __device__ __forceinline__ float tof_weight(float vh, float vl, float v
   return w * inv_norm;
 }
 
+// The weight of one TOF bin as a function of its upper edge vh alone (vl =
+// vh - D, D the bin width; units of sigma sqrt 2), tabulated: it is
+// inv_norm (erf(clamp(vh)) - erf(clamp(vh - D))) with clamp to [-vc, vc],
+// non-zero on (-vc, vc + D) and smooth between the points where an edge
+// meets the truncation (-vc, min(-vc + D, vc), max(-vc + D, vc), vc + D).
+// Each of the three pieces is cut, from its start, into intervals of width
+// exactly 1/64 (a power of two, so that the position (vh - start) * 64 is
+// exact in float32; the last interval of a piece runs past its end and
+// follows the piece's own smooth expression there) with a cubic Hermite
+// interpolant of the exact values and derivatives (error below h^4 max |4th
+// derivative| / 384, about 1e-9 of the peak weight; the float32
+// coefficients and evaluation add about 1e-7).  Evaluating it is an LDS
+// read and three FMAs instead of two erfc.  The table is built per geometry
+// by build_tof_table.
+constexpr int kTofTabMax = 1024;  // intervals
+constexpr int kTofTabPerUnit = 64;
+
+struct TofTab {
+  float b0, b1, b2, b3;  // piece boundaries
+  int n0, n1, n2;        // intervals of each piece (piece 1 starts at n0, piece 2 at n0 + n1)
+};
+
+// The table layout of a geometry with TOF (host).
+inline TofTab tof_tab_layout(const GeomDev &g) {
+  const double vc = (g.half_win - 0.5 * g.tof_bin) * g.inv_sr2, D = g.tof_bin * g.inv_sr2;
+  const double c[4] = {-vc, fmin(-vc + D, vc), fmax(-vc + D, vc), vc + D};
+  TofTab t;
+  t.b0 = (float)c[0];
+  t.b1 = (float)c[1];
+  t.b2 = (float)c[2];
+  t.b3 = (float)c[3];
+  const float b[4] = {t.b0, t.b1, t.b2, t.b3};
+  int n[3];
+  for (int p = 0; p < 3; ++p) {
+    const double w = (double)b[p + 1] - (double)b[p];
+    n[p] = w > 0.0 ? (int)ceil(w * kTofTabPerUnit) : 1;
+  }
+  t.n0 = n[0];
+  t.n1 = n[1];
+  t.n2 = n[2];
+  return t;
+}
+
+// The table layout held in registers, uniform over the wavefront (the
+// evaluation selects among its fields per lane; with the struct in kernel
+// argument memory the compiler would load the selected field per lane).
+__device__ __forceinline__ TofTab tof_tab_uniform(const TofTab &t) {
+  TofTab u;
+  u.b0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.b0)));
+  u.b1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.b1)));
+  u.b2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.b2)));
+  u.b3 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.b3)));
+  u.n0 = __builtin_amdgcn_readfirstlane(t.n0);
+  u.n1 = __builtin_amdgcn_readfirstlane(t.n1);
+  u.n2 = __builtin_amdgcn_readfirstlane(t.n2);
+  return u;
+}
+
+__host__ __device__ __forceinline__ int tof_tab_size(const TofTab &t) { return t.n0 + t.n1 + t.n2; }
+
+// The tabulated weight at vh (0 outside (b0, b3)); tab: the coefficients
+// {c0, c1, c2, c3} of c0 + s (c1 + s (c2 + s c3)) of every interval, s in
+// [0, 1) the position inside the interval.
+__device__ __forceinline__ float tof_weight_tab(const TofTab &t, const float4 *tab, float vh) {
+  const bool p2 = vh >= t.b2, p1 = vh >= t.b1;
+  const float start = p2 ? t.b2 : (p1 ? t.b1 : t.b0);
+  const int base = p2 ? t.n0 + t.n1 : (p1 ? t.n0 : 0);
+  const int nmax = p2 ? t.n2 : (p1 ? t.n1 : t.n0);
+  const float u = (vh - start) * (float)kTofTabPerUnit;
+  const int i = min(max((int)u, 0), nmax - 1);
+  const float s = u - (float)i;
+  const float4 c = tab[base + i];
+  const float w = fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
+  return (vh > t.b0 && vh < t.b3) ? w : 0.0f;
+}
+
 // One sample of a ray: plane, lower corner and weights.
 struct Sample {
   int m;        // plane along the dominant axis

@@ -600,7 +600,7 @@ constexpr int kFwdTailBlocks = 256;                   // blocks of the last buck
 // lam db - c0b) / hb in voxels; planes [mlo, mlo + nm) have lam in [0, 1].
 struct FwdLine {
   int a, nb, mlo, nm;
-  double lam0, dlam, p1b, db, c0b, hb;
+  double lam0, dlam, idlam, p1b, db, c0b, hb;
   double dxy2, ha_over_da;
 };
 
@@ -621,6 +621,7 @@ __host__ __device__ __forceinline__ FwdLine fwd_line(const GeomDev &g, int c1, i
   q.ha_over_da = ha / fabs(da);
   q.lam0 = (c0a - p1a) / da;
   q.dlam = ha / da;
+  q.idlam = da / ha;  // plane ranges only (margins of one plane absorb its rounding)
   const double m_at0 = -q.lam0 / q.dlam, m_at1 = (1.0 - q.lam0) / q.dlam;
   const double lo = fmax(0.0, ceil(fmin(m_at0, m_at1))), hi = fmin((double)(g.n[q.a] - 1), floor(fmax(m_at0, m_at1)));
   q.mlo = (int)lo;
@@ -634,26 +635,37 @@ __host__ __device__ __forceinline__ int sheet_row(int nz) { return nz + 1; }
 
 size_t fwd_sheet_bytes(const GeomDev &g) {
   const size_t nm = (size_t)std::max(g.n[0], g.n[1]);
-  return (nm * sheet_row(g.n[2]) + 2 * nm) * sizeof(float);
+  return (nm * sheet_row(g.n[2]) + 3 * nm) * sizeof(float);
 }
 
-template <bool TOF>
-__host__ __device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &q, const float *S, int nz, double A,
-                                               double B, double az, double bz, int m0, int m1, float D, int gl) {
+// TOF weights of the walks: none, the erfc evaluation, or the table.
+enum TofMode { kTofNone = 0, kTofErfc = 1, kTofTable = 2 };
+
+// The walk of one event of the line over planes m0 .. m1 (lane gl of its
+// group: m0 + gl, + 8, ...).  The TOF argument is stepped in float from its
+// double value at m0 (|vh| stays below a few units, so its float error is a
+// few 1e-7 sigma, as in the per-event walk); the z coordinate is one double
+// FMA per sample (in float, j dz a few tens of voxels along would carry
+// 1e-6 voxel errors).
+template <int TM>
+__device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &q, const float *S, int nz, float vh0,
+                                               float dvh, double u20, double du2, int m0, int m1, float D,
+                                               const TofTab &tt, const float4 *tab, int gl) {
   const int row = sheet_row(nz);
   float acc = 0.0f;
-  for (int m = m0 + gl; m <= m1; m += 8) {
-    const double lam = fma((double)m, q.dlam, q.lam0);
+  const float *sr = S + (m0 + gl - q.mlo) * row;
+  for (int j = gl; j <= m1 - m0; j += 8, sr += 8 * row) {
     float w = 1.0f;
-    if constexpr (TOF) {
-      const float vh = (float)fma(-lam, B, A);
+    if constexpr (TM == kTofErfc) {
+      const float vh = fmaf((float)j, dvh, vh0);
       w = tof_weight(vh, vh - D, g.vclip, g.inv_norm);
+    } else if constexpr (TM == kTofTable) {
+      w = tof_weight_tab(tt, tab, fmaf((float)j, dvh, vh0));
     }
-    const double u2 = fma(lam, bz, az);
+    const double u2 = fma((double)j, du2, u20);
     const double fl = floor(u2);
     const int k0 = (int)fl;
     const float f2 = (float)(u2 - fl);
-    const float *sr = S + (m - q.mlo) * row;
     const bool ok0 = (unsigned)k0 < (unsigned)nz, ok1 = (unsigned)(k0 + 1) < (unsigned)nz;
     const float t0 = sr[ok0 ? k0 : 0], t1 = sr[ok1 ? k0 + 1 : 0];
     const float s0 = ok0 ? t0 : 0.0f, s1 = ok1 ? t1 : 0.0f;
@@ -683,9 +695,9 @@ __device__ __forceinline__ float fwd_event(const GeomDev &g, const float *__rest
 // unless *cyl is set.
 __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const int *cyl, const float *__restrict__ x,
                                                              const int16_t *__restrict__ ev, const unsigned *order,
-                                                             const unsigned *off, long long nlines,
-                                                             float *__restrict__ out) {
-  extern __shared__ float sh[];
+                                                             const unsigned *off, long long nlines, TofTab tt,
+                                                             const float4 *tab, float *__restrict__ out) {
+  extern __shared__ float4 sh4[];
   if (!*cyl) return;
   const int tid = threadIdx.x, grp = tid >> 3, gl = tid & 7;
   const float D = tof_bin_width(g);
@@ -711,27 +723,49 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
   const FwdLine q = fwd_line(g, c1, c2);
   const int nz = g.n[2], row = sheet_row(nz);
   const int nm_max = max(g.n[0], g.n[1]);
-  float *S = sh;
-  int *pi1 = (int *)(sh + (size_t)nm_max * row);
-  float *pf1 = sh + (size_t)nm_max * row + nm_max;
+  // LDS: the TOF table (when given), the sheet, the planes' corners
+  const int ntab = tab ? tof_tab_size(tt) : 0;
+  float4 *tabL = sh4;
+  float *S = (float *)(sh4 + ntab);
+  int *pi1 = (int *)(S + (size_t)nm_max * row);
+  float *pf1 = S + (size_t)nm_max * row + 2 * nm_max;
+  for (int i = tid; i < ntab; i += kFwdLineBlock) tabL[i] = tab[i];
+  const TofTab tu = tof_tab_uniform(tt);
+  const AxisTerm ta = axis_term(g.lay, q.a), tb = axis_term(g.lay, 1 - q.a), tz = axis_term(g.lay, 2);
   for (int mm = tid; mm < q.nm; mm += kFwdLineBlock) {
-    const double lam = fma((double)(q.mlo + mm), q.dlam, q.lam0);
+    const int m = q.mlo + mm;
+    const double lam = fma((double)m, q.dlam, q.lam0);
     const double u1 = (q.p1b + lam * q.db - q.c0b) / q.hb;
     const double fl = floor(u1);
-    // planes whose corners both lie outside the image read nothing
-    pi1[mm] = (fl < -1.0 || fl > (double)q.nb - 1.0) ? -2 : (int)fl;
+    const int i1 = (int)fl;
+    // the layout index of the plane's two corners at z = 0 (-1: outside)
+    const bool ok0 = fl >= 0.0 && fl <= (double)q.nb - 1.0, ok1 = fl >= -1.0 && fl <= (double)q.nb - 2.0;
+    pi1[2 * mm] = ok0 ? axis_index(ta, m) + axis_index(tb, i1) : -1;
+    pi1[2 * mm + 1] = ok1 ? axis_index(ta, m) + axis_index(tb, i1 + 1) : -1;
     pf1[mm] = (float)(u1 - fl);
   }
   __syncthreads();
-  for (int t = tid; t < q.nm * nz; t += kFwdLineBlock) {
-    const int mm = t % q.nm, k = t / q.nm;  // planes fastest: along the dominant axis
-    const int m = q.mlo + mm, i1 = pi1[mm];
-    const float f1 = pf1[mm];
-    float x0 = 0.0f, x1 = 0.0f;
-    if ((unsigned)i1 < (unsigned)q.nb) x0 = x[q.a == 0 ? vidx(g.lay, m, i1, k) : vidx(g.lay, i1, m, k)];
-    if ((unsigned)(i1 + 1) < (unsigned)q.nb)
-      x1 = x[q.a == 0 ? vidx(g.lay, m, i1 + 1, k) : vidx(g.lay, i1 + 1, m, k)];
-    S[mm * row + k] = fmaf(f1, x1 - x0, x0);
+  // cells (plane, z), planes fastest; 4 cells (8 loads) per thread in flight
+  const int ncell = q.nm * nz;
+  for (int t0 = tid; t0 < ncell; t0 += 4 * kFwdLineBlock) {
+    float x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = min(t0 + u * kFwdLineBlock, ncell - 1);
+      const int mm = t % q.nm, k = t / q.nm;
+      const int zi = axis_index(tz, k), j0 = pi1[2 * mm], j1 = pi1[2 * mm + 1];
+      const float v0 = x[j0 >= 0 ? j0 + zi : 0], v1 = x[j1 >= 0 ? j1 + zi : 0];
+      x0[u] = j0 >= 0 ? v0 : 0.0f;
+      x1[u] = j1 >= 0 ? v1 : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kFwdLineBlock;
+      if (t < ncell) {
+        const int mm = t % q.nm, k = t / q.nm;
+        S[mm * row + k] = fmaf(pf1[mm], x1[u] - x0[u], x0[u]);
+      }
+    }
   }
   __syncthreads();
   const double ihz = 1.0 / g.h[2];
@@ -761,13 +795,15 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
         const double az = ((double)z1f - g.c0[2]) * ihz, bz = dz * ihz;
         double lo = q.mlo, hi = q.mlo + q.nm - 1;
         if (g.tof_on) {  // vh in [-vclip, vclip + D], one plane of margin
-          const double ma = ((A - ((double)g.vclip + D)) / B - q.lam0) / q.dlam;
-          const double mb = ((A + (double)g.vclip) / B - q.lam0) / q.dlam;
+          const double iB = 1.0 / B;
+          const double ma = ((A - ((double)g.vclip + D)) * iB - q.lam0) * q.idlam;
+          const double mb = ((A + (double)g.vclip) * iB - q.lam0) * q.idlam;
           lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
           hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
         }
         if (bz != 0.0) {  // z in (-1, nz), one plane of margin
-          const double ma = ((-1.0 - az) / bz - q.lam0) / q.dlam, mb = (((double)nz - az) / bz - q.lam0) / q.dlam;
+          const double ibz = 1.0 / bz;
+          const double ma = ((-1.0 - az) * ibz - q.lam0) * q.idlam, mb = (((double)nz - az) * ibz - q.lam0) * q.idlam;
           lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
           hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
         } else if (az <= -1.0 || az >= (double)nz) {
@@ -775,8 +811,16 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
         }
         float acc = 0.0f;
         if (hi >= lo) {
-          acc = g.tof_on ? fwd_line_walk<true>(g, q, S, nz, A, B, az, bz, (int)lo, (int)hi, D, gl)
-                         : fwd_line_walk<false>(g, q, S, nz, A, B, az, bz, (int)lo, (int)hi, D, gl);
+          const int m0 = (int)lo, m1 = (int)hi;
+          const double lam_lo = fma(lo, q.dlam, q.lam0);
+          const float vh0 = (float)(A - lam_lo * B), dvh = (float)(-q.dlam * B);
+          const double u20 = fma(lam_lo, bz, az), du2 = q.dlam * bz;
+          if (!g.tof_on)
+            acc = fwd_line_walk<kTofNone>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tt, tabL, gl);
+          else if (ntab)
+            acc = fwd_line_walk<kTofTable>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tu, tabL, gl);
+          else
+            acc = fwd_line_walk<kTofErfc>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tt, tabL, gl);
         }
         acc = group_sum<8>(acc);
         val = (float)(q.ha_over_da * dn) * acc;
@@ -784,6 +828,45 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
     }
     if (gl == 0) out[e] = val;
   }
+}
+
+// Coefficients of the TOF table (one interval per thread; see TofTab):
+// values and derivatives of the piece's own smooth expression at both ends
+// of the interval, in double.
+__global__ __launch_bounds__(256) void k_tof_table(TofTab t, double vc, double D, double inv_norm, float4 *tab) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= tof_tab_size(t)) return;
+  int j;
+  float start, end;
+  if (i < t.n0) {
+    j = i;
+    start = t.b0;
+    end = t.b1;
+  } else if (i < t.n0 + t.n1) {
+    j = i - t.n0;
+    start = t.b1;
+    end = t.b2;
+  } else {
+    j = i - t.n0 - t.n1;
+    start = t.b2;
+    end = t.b3;
+  }
+  // the evaluation maps s in [0, 1) to vh = start + (j + s) / kTofTabPerUnit
+  const double a = start + (double)j / kTofTabPerUnit, b = start + (double)(j + 1) / kTofTabPerUnit;
+  // the piece's expression (decided at the piece's middle, also for an
+  // interval that runs past the piece's end)
+  const double mid = 0.5 * ((double)start + (double)end);
+  const bool up = mid < vc;       // the upper edge inside the truncation
+  const bool lo = mid - D > -vc;  // the lower edge inside the truncation
+  const double eu = erf(vc), el = erf(-vc);
+  auto f = [&](double v) { return inv_norm * ((up ? erf(v) : eu) - (lo ? erf(v - D) : el)); };
+  auto df = [&](double v) {
+    const double two_over_sqrt_pi = 1.1283791670955126;
+    return inv_norm * two_over_sqrt_pi * ((up ? exp(-v * v) : 0.0) - (lo ? exp(-(v - D) * (v - D)) : 0.0));
+  };
+  const double h = b - a, fa = f(a), fb = f(b), da = h * df(a), db = h * df(b);
+  tab[i] = make_float4((float)fa, (float)da, (float)(3.0 * (fb - fa) - 2.0 * da - db),
+                       (float)(2.0 * (fa - fb) + da + db));
 }
 
 // The scanner is cylindrical when crystal c of ring r sits at (x_c, y_c, z_r):
@@ -882,6 +965,26 @@ int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsign
   return LM_OK;
 }
 
+int build_tof_table(const GeomDev &g, TofTab &t, float4 **tab, hipStream_t st) {
+  *tab = nullptr;
+  if (!g.tof_on) return LM_OK;
+  t = tof_tab_layout(g);
+  const int n = tof_tab_size(t);
+  if (n > kTofTabMax) return LM_OK;
+  const hipError_t e = hipMallocAsync((void **)tab, (size_t)n * sizeof(float4), st);
+  if (e == hipErrorOutOfMemory) {
+    *tab = nullptr;
+    (void)hipGetLastError();
+    return LM_OK;
+  }
+  LM_TRY_HIP(e);
+  const double vc = (g.half_win - 0.5 * g.tof_bin) * g.inv_sr2, D = g.tof_bin * g.inv_sr2;
+  const double inv_norm = 1.0 / (2.0 * std::erf(vc));
+  hipLaunchKernelGGL(k_tof_table, dim3((n + 255) / 256), dim3(256), 0, st, t, vc, D, inv_norm, *tab);
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
 int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int16_t *ev, const unsigned *order,
                      const unsigned *off, long long n, float *out, hipStream_t st, bool &queued) {
   queued = false;
@@ -893,13 +996,23 @@ int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int
     LM_TRY_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     lds_max = v;
   }
-  const size_t bytes = fwd_sheet_bytes(g);
-  if (bytes > (size_t)lds_max) return LM_OK;
+  if (fwd_sheet_bytes(g) > (size_t)lds_max) return LM_OK;
+  TofTab tt{};
+  float4 *tab = nullptr;
+  if (int rc = build_tof_table(g, tt, &tab, st)) return rc;
+  size_t bytes = fwd_sheet_bytes(g) + (tab ? (size_t)tof_tab_size(tt) * sizeof(float4) : 0);
+  if (bytes > (size_t)lds_max) {  // the sheet alone fits: erfc weights
+    if (tab) (void)hipFreeAsync(tab, st);
+    tab = nullptr;
+    bytes = fwd_sheet_bytes(g);
+  }
   const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
   const long long nb = 8 * ((nlines + 7) / 8) + kFwdTailBlocks;
   hipLaunchKernelGGL(k_fwd_lines, dim3((unsigned)nb), dim3(kFwdLineBlock), bytes, st, g, cyl, x, ev, order, off,
-                     nlines, out);
-  LM_TRY_HIP(hipGetLastError());
+                     nlines, tt, tab, out);
+  const hipError_t e = hipGetLastError();
+  if (tab) (void)hipFreeAsync(tab, st);  // a release error has no caller to go to
+  LM_TRY_HIP(e);
   queued = true;
   return LM_OK;
 }
