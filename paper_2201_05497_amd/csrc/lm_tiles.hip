@@ -257,21 +257,13 @@ __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, in
   }
 }
 
-// LDS position of voxel (li, lj, lk) of a tile: its brick (2 x 2 x 2 per
-// tile, x fastest) times 64 plus its place in the brick, the order of the
-// plan's layout.
-__device__ __forceinline__ int tile_lidx(int li, int lj, int lk) {
-  const int b = ((lk >> 2) * 2 + (lj >> 2)) * 2 + (li >> 2);
-  return (b << 6) | ((lk & 3) << 4) | ((lj & 3) << 2) | (li & 3);
-}
-
 struct SegLane {
   int4 h0;
   float4 h1;
   float v;
 };
 
-__device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, long long k, int jp) {
+__device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, unsigned k, int jp) {
   SegLane s;
   const TileRec *r = recs + k;
   s.h0 = r->h0;
@@ -280,9 +272,39 @@ __device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, lo
   return s;
 }
 
+// The voxel of lane (jp, corner) for record s on a tile at (tx, ty, tz):
+// its tile-local row-major index (li + 8 lj + 64 lk) and value, or add = 0.
+// The sample and corner arithmetic is that of sample_at / corner().
+__device__ __forceinline__ void seg_voxel(const SegLane &s, int jp, int corner, int tx, int ty, int tz, int nx, int ny,
+                                          int nz, float &add, int &at) {
+  add = 0.0f;
+  at = 0;
+  if (s.v == 0.0f) return;
+  const int m0 = s.h0.x & 1023, np = (s.h0.x >> 10) & 1023, a = s.h0.x >> 20;
+  const int ta = a == 0 ? tx : (a == 1 ? ty : tz);
+  const int m = ta * kTE + jp;
+  const int j = m - m0;
+  if ((unsigned)j >= (unsigned)np) return;
+  const float fj = (float)j;
+  const float u1 = fmaf(fj, s.h1.y, s.h1.x), u2 = fmaf(fj, s.h1.w, s.h1.z);
+  const float fl1 = floorf(u1), fl2 = floorf(u2);
+  const float f1 = u1 - fl1, f2 = u2 - fl2;
+  const int c1 = s.h0.y + (int)fl1 + (corner & 1), c2 = s.h0.z + (int)fl2 + (corner >> 1);
+  const float wc = ((corner & 1) ? f1 : 1.0f - f1) * ((corner & 2) ? f2 : 1.0f - f2);
+  const int i = a == 0 ? m : c1;
+  const int jj = a == 0 ? c1 : (a == 1 ? m : c2);
+  const int kk = a == 2 ? m : c2;
+  const int li = i - tx * kTE, lj = jj - ty * kTE, lk = kk - tz * kTE;
+  if ((unsigned)(li | lj | lk) >= (unsigned)kTE || i >= nx || jj >= ny || kk >= nz || wc == 0.0f) return;
+  add = s.v * wc;
+  at = li + kTE * (lj + kTE * lk);
+}
+
 // Phase 2: one workgroup per tile; recs are the subset's records, seg the
-// record numbers of every tile, off the subset's per-tile ranges of seg
-// (the subset's first at off[0]).
+// record numbers of every tile, off the subset's per-tile ranges of seg.
+// Each wavefront takes records two at a time (one per half), unrolled by
+// two with alternating buffers so that the next records' loads are in
+// flight while the current ones are added.
 __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, const int *__restrict__ order,
                                                        const long long *__restrict__ off,
                                                        const unsigned *__restrict__ seg,
@@ -295,8 +317,8 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
   const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, tz = tile / (tg.ntx * tg.nty);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const int jp = hl >> 2, corner = hl & 3;
-  // this thread's voxel of the tile in the plan's brick layout; its image
-  // values are loaded now and used at the end
+  // this thread's voxel of the tile (threads in the plan's brick order);
+  // its image values are loaded now and used at the end
   const Layout &L = g.lay;
   const int v = threadIdx.x;
   const int b = (v >> 6) & 7, bi = tx * 2 + (b & 1), bj = ty * 2 + ((b >> 1) & 1), bk = tz * 2 + (b >> 2);
@@ -314,62 +336,53 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
   for (int i = threadIdx.x; i < 2 * kWaves2 * kTV; i += kBlock2) all[i] = 0.0f;
   __syncthreads();
   float *mine = acc[2 * wv + half];
-  const long long s0 = off[tile], s1 = off[tile + 1];
+  const long long s0 = off[tile];
+  const int cnt = (int)(off[tile + 1] - s0);
+  const unsigned *tseg = seg + s0;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  constexpr long long kStep = 2 * kWaves2;
-  long long k = s0 + 2 * wv + half;
-  unsigned idx_nxt = (k + kStep < s1) ? seg[k + kStep] : 0u;
-  SegLane cur = {};
-  if (k < s1) cur = load_seg(recs, seg[k], jp);
-  for (long long kb = s0 + 2 * wv; kb < s1; kb += kStep) {
-    const long long kn = k + kStep, knn = k + 2 * kStep;
-    const unsigned idx_nn = (knn < s1) ? seg[knn] : 0u;    // two steps ahead
-    SegLane nxt = {};
-    if (kn < s1) nxt = load_seg(recs, idx_nxt, jp);       // one step ahead
-    float add = 0.0f;
-    int at = 0;
-    if (k < s1 && cur.v != 0.0f) {
-      const int m0 = cur.h0.x & 1023, np = (cur.h0.x >> 10) & 1023, a = cur.h0.x >> 20;
-      const int I1 = cur.h0.y, I2 = cur.h0.z;
-      const float F1 = cur.h1.x, V1 = cur.h1.y, F2 = cur.h1.z, V2 = cur.h1.w;
-      const int ta = a == 0 ? tx : (a == 1 ? ty : tz);
-      const int m = ta * kTE + jp;
-      const int j = m - m0;
-      if (j >= 0 && j < np) {
-        // the sample and corner of sample_at / corner()
-        const float u1 = fmaf((float)j, V1, F1), u2 = fmaf((float)j, V2, F2);
-        const float fl1 = floorf(u1), fl2 = floorf(u2);
-        const float f1 = u1 - fl1, f2 = u2 - fl2;
-        const int c1 = I1 + (int)fl1 + (corner & 1), c2 = I2 + (int)fl2 + (corner >> 1);
-        const float wc = ((corner & 1) ? f1 : 1.0f - f1) * ((corner & 2) ? f2 : 1.0f - f2);
-        const int i = a == 0 ? m : c1;
-        const int jj = a == 0 ? c1 : (a == 1 ? m : c2);
-        const int kk = a == 2 ? m : c2;
-        const int li = i - tx * kTE, lj = jj - ty * kTE, lk = kk - tz * kTE;
-        if ((unsigned)li < (unsigned)kTE && (unsigned)lj < (unsigned)kTE && (unsigned)lk < (unsigned)kTE &&
-            i < nx && jj < ny && kk < nz && wc != 0.0f) {
-          add = cur.v * wc;
-          at = tile_lidx(li, lj, lk);
-        }
-      }
+  constexpr int kStep = 2 * kWaves2;
+  const int k0 = 2 * wv + half;
+  if (cnt > 0) {
+    // indices are clamped to the last record so that every load is valid;
+    // records past the end are not added
+    auto idx = [&](int k) { return tseg[min(k, cnt - 1)]; };
+    // in issue order, an index is loaded before the records that are in
+    // flight when it is needed, so waiting for it leaves them in flight
+    unsigned iB = idx(k0 + kStep);
+    SegLane A = load_seg(recs, idx(k0), jp);
+    unsigned iC = idx(k0 + 2 * kStep);
+    for (int k = k0; k - k0 < cnt; k += 2 * kStep) {
+      const SegLane B = load_seg(recs, iB, jp);
+      const unsigned iD = idx(k + 3 * kStep);
+      float add;
+      int at;
+      seg_voxel(A, jp, corner, tx, ty, tz, nx, ny, nz, add, at);
+      // the 32 lanes of a record touch distinct voxels of their own copy; a
+      // lane may read a word another lane of the wavefront wrote before,
+      // which the wavefront's in-order LDS operations deliver once the
+      // compiler keeps the order (the fences)
+      if (k < cnt && add != 0.0f) mine[at] += add;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      A = load_seg(recs, iC, jp);
+      iC = idx(k + 4 * kStep);
+      seg_voxel(B, jp, corner, tx, ty, tz, nx, ny, nz, add, at);
+      if (k + kStep < cnt && add != 0.0f) mine[at] += add;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      iB = iD;
     }
-    // the 32 lanes of a record touch distinct voxels of their own copy; a
-    // lane may read a word another lane of the wavefront wrote in the
-    // previous iteration, which the wavefront's in-order LDS operations
-    // deliver once the compiler keeps the order (the fences)
-    if (add != 0.0f) mine[at] += add;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    cur = nxt;
-    idx_nxt = idx_nn;
-    k = kn;
   }
   __syncthreads();
   if (!mine_vox) return;
+  // voxel v of the brick-ordered tile: row-major position in the copies
+  const int lv = (b & 1) * 4 + (v & 3) + kTE * (((b >> 1) & 1) * 4 + ((v >> 2) & 3)) +
+                 kTE * kTE * ((b >> 2) * 4 + ((v >> 4) & 3));
   float d = 0.0f;
-#pragma unroll 8
-  for (int c = 0; c < 2 * kWaves2; ++c) d += acc[c][v];
+#pragma unroll
+  for (int c = 0; c < 2 * kWaves2; ++c) d += acc[c][lv];
   if (dz_out) {
     dz_out[gi] = d;
     return;

@@ -26,7 +26,9 @@ Three cases:
 Usage: ``python -m tests.golden.full_size compute c2|c3|sens`` (minutes to
 about half an hour of one core each; raw results go to ``.cache/``), then
 ``python -m tests.golden.full_size pack`` writes the ``.npz`` files of this
-directory from them.
+directory from them.  ``python -m tests.golden.full_size sensitivity``
+(after ``compute c2``; about an hour) writes ``c2_sensitivity.json``, the
+oracle's own sensitivity of c2 to float32 rounding of its state.
 """
 from __future__ import annotations
 
@@ -170,6 +172,47 @@ def compute_sens():
     np.savez(os.path.join(RAW, "sens.npz"), g=g)
 
 
+def compute_c2_sensitivity():
+    """The oracle's own sensitivity on c2: the same five epochs with its
+    state (x, z, zbar, w and y) rounded to float32 after every update,
+    against the stored FP64 run (``compute c2`` first).  Writes
+    ``c2_sensitivity.json``: the sup-norm differences of x (after the last
+    epoch), z, and of the TV dual w over the stored slices (relative L2 and
+    sup norm over beta).  The TV dual is the ill-conditioned quantity: where
+    K x is nearly zero its direction follows tiny gradients."""
+    import json
+    import oracle
+    raw = np.load(os.path.join(RAW, "c2.npz"))
+    p, g = c2_inputs()
+    G = oracle.Geometry.from_problem(p)
+    n = C2["n_sub"]
+    t0 = time.time()
+    su = oracle.lm_setup(G, p.events, n, g.astype(np.float64), gamma_of(p.x0), C2["rho"])
+    s = p.s.astype(np.float64)
+    st = oracle.lm_init(G, p.events, s, su, p.x0)
+
+    def f32(v):
+        return v.astype(np.float32).astype(np.float64)
+
+    for ep in range(C2["epochs"]):
+        for i in c2_sequence(ep):
+            oracle.lm_update(G, p.events, s, su, st, int(i), n, C2["beta"])
+            st.x, st.z, st.zbar, st.w = f32(st.x), f32(st.z), f32(st.zbar), f32(st.w)
+            st.y = 1.0 - f32(1.0 - st.y)
+        _log(f"c2 sensitivity epoch {ep + 1} {time.time() - t0:.0f} s")
+    x5 = raw[f"x{C2['epochs']}"].astype(np.float64)
+    zr = raw["z"].astype(np.float64)
+    wr = raw["w"].astype(np.float64)
+    wp = st.w[:, list(C2["w_slices"])]
+    out = {"x_inf": float(np.abs(st.x - x5).max() / np.abs(x5).max()),
+           "z_inf": float(np.abs(st.z - zr).max() / np.abs(zr).max()),
+           "w_l2": float(np.linalg.norm(wp - wr) / np.linalg.norm(wr)),
+           "w_inf_over_beta": float(np.abs(wp - wr).max() / C2["beta"])}
+    with open(os.path.join(HERE, "c2_sensitivity.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    _log(f"c2 sensitivity {out}")
+
+
 # ----------------------------------------------------------------- storage
 #
 # Images are stored as integers on a grid of 2^-18 of their largest
@@ -254,5 +297,7 @@ if __name__ == "__main__":
         {"c2": compute_c2, "c3": compute_c3, "sens": compute_sens}[sys.argv[2]]()
     elif what == "pack":
         pack()
+    elif what == "sensitivity":
+        compute_c2_sensitivity()
     else:
         sys.exit(__doc__)
