@@ -294,13 +294,16 @@ __host__ __device__ __forceinline__ float tof_weight(float vh, float vl, float v
   vl = fminf(fmaxf(vl, -vclip), vclip);
   const float eh = erfc_fit(fabsf(vh));
   const float el = erfc_fit(fabsf(vl));
-  // selects rather than branches (same values): el - eh on the positive
-  // side, its negation eh - el on the negative side, 2 - el - eh across 0
+  // selects rather than branches: el - eh on the positive side, its
+  // negation eh - el on the negative side, 2 - el - eh across 0.  The
+  // weight of a bin is never negative; where the two erfc values nearly
+  // cancel (far tails) the rounding of their difference can be, and is
+  // clamped.
   const float d = el - eh;
   const float same = (vl >= 0.0f) ? d : -d;
   const float across = (2.0f - el) - eh;
   const float w = (vl >= 0.0f || vh <= 0.0f) ? same : across;
-  return w * inv_norm;
+  return fmaxf(w, 0.0f) * inv_norm;
 }
 
 // The weight of one TOF bin as a function of its upper edge vh alone (vl =
@@ -376,7 +379,9 @@ __device__ __forceinline__ float tof_weight_tab(const TofTab &t, const float4 *t
   const float s = u - (float)i;
   const float4 c = tab[base + i];
   const float w = fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
-  return (vh > t.b0 && vh < t.b3) ? w : 0.0f;
+  // near the ends of the support the cubic of a weight that falls to 0 can
+  // round below it
+  return (vh > t.b0 && vh < t.b3) ? fmaxf(w, 0.0f) : 0.0f;
 }
 
 // One sample of a ray: plane, lower corner and weights.

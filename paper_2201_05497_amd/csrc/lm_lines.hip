@@ -123,17 +123,25 @@ struct ZPart {
   int zlo, zc;
 };
 
-// Adds one LOR's samples at the lane's plane to the lane's column.  wfull is
-// the weight of a sample whose TOF argument covers the whole truncated
-// Gaussian (vh >= vclip and vl <= -vclip), the same value tof_weight gives
-// for it, so that such samples skip the two erfc evaluations.
+// Adds one LOR's samples at the lane's plane to the lane's column.  With a
+// TOF table (single bins) the weight is read from it; otherwise wfull is the
+// weight of a sample whose TOF argument covers the whole truncated Gaussian
+// (vh >= vclip and vl <= -vclip), the same value tof_weight gives for it, so
+// that such samples skip the two erfc evaluations.
+template <bool TAB>
 __device__ __forceinline__ void add_lor(const GeomDev &g, const LineLane &q, const Lor &o, const ZPart &zp,
-                                        float wfull, float *acc, int nz, int lane) {
+                                        float wfull, const TofTab &tt, const float4 *tab, float *acc, int nz,
+                                        int lane) {
   if (!q.active) return;
   float c = o.c;
   if (g.tof_on) {
-    const float vh = (float)fma(-q.lam, o.B, o.A), vl = vh - o.D;
-    c *= (vh >= g.vclip && vl <= -g.vclip) ? wfull : tof_weight(vh, vl, g.vclip, g.inv_norm);
+    const float vh = (float)fma(-q.lam, o.B, o.A);
+    if constexpr (TAB) {
+      c *= tof_weight_tab(tt, tab, vh);
+    } else {
+      const float vl = vh - o.D;
+      c *= (vh >= g.vclip && vl <= -g.vclip) ? wfull : tof_weight(vh, vl, g.vclip, g.inv_norm);
+    }
   }
   if (c == 0.0f) return;
   const double u2 = fma(q.lam, o.bz, o.az);
@@ -295,7 +303,7 @@ __global__ __launch_bounds__(kLanes) void k_sens_lines(GeomDev g, const int *cyl
       while (m) {
         const int j = __ffsll((long long)m) - 1;
         m &= m - 1;
-        add_lor(g, q, broadcast(o, j), zp, wfull, acc, nz, lane);
+        add_lor<false>(g, q, broadcast(o, j), zp, wfull, TofTab{}, nullptr, acc, nz, lane);
       }
     }
   }
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int *cyl, c
 // values when its TOF window or its z range misses the chunk and part.
 __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const int *cyl, const unsigned *off,
                                                        const LineRec *rec, long long p0, long long nlines, int nchunk,
-                                                       int nzp, float *img) {
+                                                       int nzp, TofTab tt, const float4 *tab, float *img) {
   __shared__ float acc[2 * kZPart * kLanes];
   if (!*cyl) return;
   const long long blk = (long long)blockIdx.x;
@@ -479,6 +487,7 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const int *cyl
   for (int i = lane; i < 2 * zp.zc * kLanes; i += kLanes) acc[i] = 0.0f;
   const double edge = 0.5 * g.tof_bin;
   const float wfull = tof_weight(g.vclip, -g.vclip, g.vclip, g.inv_norm);
+  const TofTab tu = tof_tab_uniform(tt);
   const double ihz = 1.0 / g.h[2];
   // 64 events at a time: each lane loads one event and tests it (z range,
   // TOF window) for this chunk and part, then the wavefront adds the events
@@ -513,7 +522,10 @@ __global__ __launch_bounds__(kLanes) void k_back_lines(GeomDev g, const int *cyl
     while (m) {
       const int j = __ffsll((long long)m) - 1;
       m &= m - 1;
-      add_lor(g, q, broadcast(o, j), zp, wfull, acc, nz, lane);
+      if (tab)
+        add_lor<true>(g, q, broadcast(o, j), zp, wfull, tu, tab, acc, nz, lane);
+      else
+        add_lor<false>(g, q, broadcast(o, j), zp, wfull, tu, tab, acc, nz, lane);
     }
   }
   flush(g, q, zp, acc, img, lane);
@@ -641,28 +653,126 @@ size_t fwd_sheet_bytes(const GeomDev &g) {
 // TOF weights of the walks: none, the erfc evaluation, or the table.
 enum TofMode { kTofNone = 0, kTofErfc = 1, kTofTable = 2 };
 
-// The walk of one event of the line over planes m0 .. m1 (lane gl of its
-// group: m0 + gl, + 8, ...).  The TOF argument is stepped in float from its
-// double value at m0 (|vh| stays below a few units, so its float error is a
-// few 1e-7 sigma, as in the per-event walk); the z coordinate is one double
-// FMA per sample (in float, j dz a few tens of voxels along would carry
-// 1e-6 voxel errors).
+// LDS of a line block: the TOF table (when given), the sheet [plane][z]
+// (rows of sheet_row(nz) floats), each plane's two transaxial corners as
+// layout indices at z = 0 (-1: outside the image) and the fraction f1.
+struct SheetLds {
+  float4 *tab;
+  int ntab;
+  float *S;
+  int *idx;
+  float *f1;
+};
+
+__device__ __forceinline__ SheetLds sheet_lds(float4 *sh4, const GeomDev &g, int ntab) {
+  const int nm_max = max(g.n[0], g.n[1]), row = sheet_row(g.n[2]);
+  SheetLds L;
+  L.tab = sh4;
+  L.ntab = ntab;
+  L.S = (float *)(sh4 + ntab);
+  L.idx = (int *)(L.S + (size_t)nm_max * row);
+  L.f1 = L.S + (size_t)nm_max * row + 2 * nm_max;
+  return L;
+}
+
+// The transaxial corners of the line's planes (one plane per thread).
+__device__ __forceinline__ void sheet_corners(const GeomDev &g, const FwdLine &q, const SheetLds &L, int tid) {
+  const AxisTerm ta = axis_term(g.lay, q.a), tb = axis_term(g.lay, 1 - q.a);
+  for (int mm = tid; mm < q.nm; mm += kFwdLineBlock) {
+    const int m = q.mlo + mm;
+    const double lam = fma((double)m, q.dlam, q.lam0);
+    const double u1 = (q.p1b + lam * q.db - q.c0b) / q.hb;
+    const double fl = floor(u1);
+    const int i1 = (int)fl;
+    const bool ok0 = fl >= 0.0 && fl <= (double)q.nb - 1.0, ok1 = fl >= -1.0 && fl <= (double)q.nb - 2.0;
+    L.idx[2 * mm] = ok0 ? axis_index(ta, m) + axis_index(tb, i1) : -1;
+    L.idx[2 * mm + 1] = ok1 ? axis_index(ta, m) + axis_index(tb, i1 + 1) : -1;
+    L.f1[mm] = (float)(u1 - fl);
+  }
+}
+
+// A LOR of a line (ring z's z1, z2 and TOF bin k in the line's orientation):
+// the planes it can touch, m0 .. m1 (m1 < m0: none), its TOF argument vh0 +
+// j dvh and z coordinate u20 + j du2 (voxels) at plane m0 + j, and its plane
+// length L.  The TOF argument is stepped in float from its double value at
+// m0 (|vh| stays below a few units, so its float error is a few 1e-7 sigma,
+// as in the per-event walk); z takes one double FMA per sample (in float, j
+// dz a few tens of voxels along would carry 1e-6 voxel errors).
+struct LineLor {
+  int m0, m1;
+  float vh0, dvh;
+  double u20, du2;
+  float L;
+};
+
+__device__ __forceinline__ LineLor line_lor(const GeomDev &g, const FwdLine &q, float z1f, float z2f, int k, float D,
+                                            double ihz) {
+  const int nz = g.n[2];
+  const double dz = (double)z2f - z1f;
+  const double dn = sqrt(q.dxy2 + dz * dz);
+  // vh(lam) = A - lam B (units of sigma sqrt 2), z(lam) = az + lam bz (voxels)
+  const double A = (k * g.tof_bin + 0.5 * g.tof_bin + 0.5 * dn) * g.inv_sr2, B = dn * g.inv_sr2;
+  const double az = ((double)z1f - g.c0[2]) * ihz, bz = dz * ihz;
+  double lo = q.mlo, hi = q.mlo + q.nm - 1;
+  if (g.tof_on) {  // vh in [-vclip, vclip + D], one plane of margin
+    const double iB = 1.0 / B;
+    const double ma = ((A - ((double)g.vclip + D)) * iB - q.lam0) * q.idlam;
+    const double mb = ((A + (double)g.vclip) * iB - q.lam0) * q.idlam;
+    lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
+    hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
+  }
+  if (bz != 0.0) {  // z in (-1, nz), one plane of margin
+    const double ibz = 1.0 / bz;
+    const double ma = ((-1.0 - az) * ibz - q.lam0) * q.idlam, mb = (((double)nz - az) * ibz - q.lam0) * q.idlam;
+    lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
+    hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
+  } else if (az <= -1.0 || az >= (double)nz) {
+    hi = lo - 1.0;
+  }
+  LineLor o;
+  o.L = (float)(q.ha_over_da * dn);
+  o.vh0 = o.dvh = 0.0f;
+  o.u20 = o.du2 = 0.0;
+  if (hi >= lo) {
+    o.m0 = (int)lo;
+    o.m1 = (int)hi;
+    const double lam_lo = fma(lo, q.dlam, q.lam0);
+    o.vh0 = (float)(A - lam_lo * B);
+    o.dvh = (float)(-q.dlam * B);
+    o.u20 = fma(lam_lo, bz, az);
+    o.du2 = q.dlam * bz;
+  } else {
+    o.m0 = q.mlo;
+    o.m1 = q.mlo - 1;
+  }
+  return o;
+}
+
+// The TOF weight of a line walk's sample.
 template <int TM>
-__device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &q, const float *S, int nz, float vh0,
-                                               float dvh, double u20, double du2, int m0, int m1, float D,
-                                               const TofTab &tt, const float4 *tab, int gl) {
+__device__ __forceinline__ float line_weight(const GeomDev &g, const LineLor &o, int j, float D, const TofTab &tt,
+                                             const float4 *tab) {
+  if constexpr (TM == kTofErfc) {
+    const float vh = fmaf((float)j, o.dvh, o.vh0);
+    return tof_weight(vh, vh - D, g.vclip, g.inv_norm);
+  } else if constexpr (TM == kTofTable) {
+    return tof_weight_tab(tt, tab, fmaf((float)j, o.dvh, o.vh0));
+  } else {
+    return 1.0f;
+  }
+}
+
+// The forward walk of one LOR of the line over its planes (lane gl of its
+// group: m0 + gl, + 8, ...): the sum of w (lerp in z of the sheet).
+template <int TM>
+__device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &q, const float *S, int nz,
+                                               const LineLor &o, float D, const TofTab &tt, const float4 *tab, int gl) {
   const int row = sheet_row(nz);
   float acc = 0.0f;
-  const float *sr = S + (m0 + gl - q.mlo) * row;
-  for (int j = gl; j <= m1 - m0; j += 8, sr += 8 * row) {
-    float w = 1.0f;
-    if constexpr (TM == kTofErfc) {
-      const float vh = fmaf((float)j, dvh, vh0);
-      w = tof_weight(vh, vh - D, g.vclip, g.inv_norm);
-    } else if constexpr (TM == kTofTable) {
-      w = tof_weight_tab(tt, tab, fmaf((float)j, dvh, vh0));
-    }
-    const double u2 = fma((double)j, du2, u20);
+  const float *sr = S + (o.m0 + gl - q.mlo) * row;
+  for (int j = gl; j <= o.m1 - o.m0; j += 8, sr += 8 * row) {
+    const float w = line_weight<TM>(g, o, j, D, tt, tab);
+    const double u2 = fma((double)j, o.du2, o.u20);
     const double fl = floor(u2);
     const int k0 = (int)fl;
     const float f2 = (float)(u2 - fl);
@@ -673,6 +783,7 @@ __device__ __forceinline__ float fwd_line_walk(const GeomDev &g, const FwdLine &
   }
   return acc;
 }
+
 
 // Per-event projection of event e by a group (the per-event projector's
 // walk over the image x); 0 for an invalid event.
@@ -722,30 +833,13 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
   pair_of(blk, g.n_cry, c1, c2);
   const FwdLine q = fwd_line(g, c1, c2);
   const int nz = g.n[2], row = sheet_row(nz);
-  const int nm_max = max(g.n[0], g.n[1]);
-  // LDS: the TOF table (when given), the sheet, the planes' corners
-  const int ntab = tab ? tof_tab_size(tt) : 0;
-  float4 *tabL = sh4;
-  float *S = (float *)(sh4 + ntab);
-  int *pi1 = (int *)(S + (size_t)nm_max * row);
-  float *pf1 = S + (size_t)nm_max * row + 2 * nm_max;
-  for (int i = tid; i < ntab; i += kFwdLineBlock) tabL[i] = tab[i];
+  const SheetLds L = sheet_lds(sh4, g, tab ? tof_tab_size(tt) : 0);
+  for (int i = tid; i < L.ntab; i += kFwdLineBlock) L.tab[i] = tab[i];
   const TofTab tu = tof_tab_uniform(tt);
-  const AxisTerm ta = axis_term(g.lay, q.a), tb = axis_term(g.lay, 1 - q.a), tz = axis_term(g.lay, 2);
-  for (int mm = tid; mm < q.nm; mm += kFwdLineBlock) {
-    const int m = q.mlo + mm;
-    const double lam = fma((double)m, q.dlam, q.lam0);
-    const double u1 = (q.p1b + lam * q.db - q.c0b) / q.hb;
-    const double fl = floor(u1);
-    const int i1 = (int)fl;
-    // the layout index of the plane's two corners at z = 0 (-1: outside)
-    const bool ok0 = fl >= 0.0 && fl <= (double)q.nb - 1.0, ok1 = fl >= -1.0 && fl <= (double)q.nb - 2.0;
-    pi1[2 * mm] = ok0 ? axis_index(ta, m) + axis_index(tb, i1) : -1;
-    pi1[2 * mm + 1] = ok1 ? axis_index(ta, m) + axis_index(tb, i1 + 1) : -1;
-    pf1[mm] = (float)(u1 - fl);
-  }
+  sheet_corners(g, q, L, tid);
   __syncthreads();
   // cells (plane, z), planes fastest; 4 cells (8 loads) per thread in flight
+  const AxisTerm tz = axis_term(g.lay, 2);
   const int ncell = q.nm * nz;
   for (int t0 = tid; t0 < ncell; t0 += 4 * kFwdLineBlock) {
     float x0[4], x1[4];
@@ -753,7 +847,7 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
     for (int u = 0; u < 4; ++u) {
       const int t = min(t0 + u * kFwdLineBlock, ncell - 1);
       const int mm = t % q.nm, k = t / q.nm;
-      const int zi = axis_index(tz, k), j0 = pi1[2 * mm], j1 = pi1[2 * mm + 1];
+      const int zi = axis_index(tz, k), j0 = L.idx[2 * mm], j1 = L.idx[2 * mm + 1];
       const float v0 = x[j0 >= 0 ? j0 + zi : 0], v1 = x[j1 >= 0 ? j1 + zi : 0];
       x0[u] = j0 >= 0 ? v0 : 0.0f;
       x1[u] = j1 >= 0 ? v1 : 0.0f;
@@ -763,7 +857,7 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
       const int t = t0 + u * kFwdLineBlock;
       if (t < ncell) {
         const int mm = t % q.nm, k = t / q.nm;
-        S[mm * row + k] = fmaf(pf1[mm], x1[u] - x0[u], x0[u]);
+        L.S[mm * row + k] = fmaf(L.f1[mm], x1[u] - x0[u], x0[u]);
       }
     }
   }
@@ -788,47 +882,24 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
         float acc = fwd_event(g, x, r, D, gl);
         val = group_sum<8>(acc);
       } else {
-        const double dz = (double)z2f - z1f;
-        const double dn = sqrt(q.dxy2 + dz * dz);
-        // vh(lam) = A - lam B (units of sigma sqrt 2), z(lam) = az + lam bz (voxels)
-        const double A = (k * g.tof_bin + 0.5 * g.tof_bin + 0.5 * dn) * g.inv_sr2, B = dn * g.inv_sr2;
-        const double az = ((double)z1f - g.c0[2]) * ihz, bz = dz * ihz;
-        double lo = q.mlo, hi = q.mlo + q.nm - 1;
-        if (g.tof_on) {  // vh in [-vclip, vclip + D], one plane of margin
-          const double iB = 1.0 / B;
-          const double ma = ((A - ((double)g.vclip + D)) * iB - q.lam0) * q.idlam;
-          const double mb = ((A + (double)g.vclip) * iB - q.lam0) * q.idlam;
-          lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
-          hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
-        }
-        if (bz != 0.0) {  // z in (-1, nz), one plane of margin
-          const double ibz = 1.0 / bz;
-          const double ma = ((-1.0 - az) * ibz - q.lam0) * q.idlam, mb = (((double)nz - az) * ibz - q.lam0) * q.idlam;
-          lo = fmax(lo, floor(fmin(ma, mb)) - 1.0);
-          hi = fmin(hi, ceil(fmax(ma, mb)) + 1.0);
-        } else if (az <= -1.0 || az >= (double)nz) {
-          hi = lo - 1.0;
-        }
+        const LineLor o = line_lor(g, q, z1f, z2f, k, D, ihz);
         float acc = 0.0f;
-        if (hi >= lo) {
-          const int m0 = (int)lo, m1 = (int)hi;
-          const double lam_lo = fma(lo, q.dlam, q.lam0);
-          const float vh0 = (float)(A - lam_lo * B), dvh = (float)(-q.dlam * B);
-          const double u20 = fma(lam_lo, bz, az), du2 = q.dlam * bz;
+        if (o.m1 >= o.m0) {
           if (!g.tof_on)
-            acc = fwd_line_walk<kTofNone>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tt, tabL, gl);
-          else if (ntab)
-            acc = fwd_line_walk<kTofTable>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tu, tabL, gl);
+            acc = fwd_line_walk<kTofNone>(g, q, L.S, nz, o, D, tu, L.tab, gl);
+          else if (L.ntab)
+            acc = fwd_line_walk<kTofTable>(g, q, L.S, nz, o, D, tu, L.tab, gl);
           else
-            acc = fwd_line_walk<kTofErfc>(g, q, S, nz, vh0, dvh, u20, du2, m0, m1, D, tt, tabL, gl);
+            acc = fwd_line_walk<kTofErfc>(g, q, L.S, nz, o, D, tu, L.tab, gl);
         }
         acc = group_sum<8>(acc);
-        val = (float)(q.ha_over_da * dn) * acc;
+        val = o.L * acc;
       }
     }
     if (gl == 0) out[e] = val;
   }
 }
+
 
 // Coefficients of the TOF table (one interval per thread; see TofTab):
 // values and derivatives of the piece's own smooth expression at both ends
@@ -965,6 +1036,14 @@ int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsign
   return LM_OK;
 }
 
+// The largest LDS allocation of a block on the current device.
+static int lds_per_block(int &bytes) {
+  int dev = 0;
+  LM_TRY_HIP(hipGetDevice(&dev));
+  LM_TRY_HIP(hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  return LM_OK;
+}
+
 int build_tof_table(const GeomDev &g, TofTab &t, float4 **tab, hipStream_t st) {
   *tab = nullptr;
   if (!g.tof_on) return LM_OK;
@@ -989,13 +1068,8 @@ int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int
                      const unsigned *off, long long n, float *out, hipStream_t st, bool &queued) {
   queued = false;
   if (!lines_possible(g) || n == 0) return LM_OK;
-  static int lds_max = -1;  // the largest LDS allocation of a block (device 0's)
-  if (lds_max < 0) {
-    int dev = 0, v = 0;
-    LM_TRY_HIP(hipGetDevice(&dev));
-    LM_TRY_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    lds_max = v;
-  }
+  int lds_max = 0;
+  if (int rc = lds_per_block(lds_max)) return rc;
   if (fwd_sheet_bytes(g) > (size_t)lds_max) return LM_OK;
   TofTab tt{};
   float4 *tab = nullptr;
@@ -1067,12 +1141,21 @@ int launch_back_lines(const GeomDev &g, const int *cyl, const float *v, const in
   const int nchunk = (na_max + kLanes - 1) / kLanes;
   const int nzp = (g.n[2] + kZPart - 1) / kZPart;
   const long long per = std::max<long long>(1, (1LL << 24) / ((long long)nchunk * nzp));
+  TofTab tt{};
+  float4 *tab = nullptr;
+  if (e == hipSuccess) {
+    if (int rc = build_tof_table(g, tt, &tab, st)) {
+      release();
+      return rc;
+    }
+  }
   for (long long p0 = 0; e == hipSuccess && p0 < nlines; p0 += per) {
     const long long m = std::min(per, nlines - p0);
     hipLaunchKernelGGL(k_back_lines, dim3((unsigned)(m * nchunk * nzp)), dim3(kLanes), 0, st, g, cyl, off, rec, p0,
-                       m, nchunk, nzp, img);
+                       m, nchunk, nzp, tt, tab, img);
     e = hipGetLastError();
   }
+  if (tab) (void)hipFreeAsync(tab, st);  // a release error has no caller to go to
   if (e == hipSuccess) {
     // 4096 blocks of 4 wavefronts stride over the list
     const long long nb = std::min<long long>(4096, (n + 4 * kLanes - 1) / (4 * kLanes));
