@@ -30,7 +30,11 @@ Readings of the paper taken here, where it is silent or ambiguous:
   with the full projection D and the same ||grad|| as the norm bound;
 * T = min over the subset step sizes and the prior step size:
   T_j = rho / (2 gamma max(g_j, ||K||)) with p_k = 1/(2n), p_prior = 1/2;
-  S_e = gamma rho / (P^LM 1)_e, and 0 where (P^LM 1)_e = 0;
+  S_e = gamma rho / (P^LM 1)_e, and 0 where the LOR misses the image,
+  read as (P^LM 1)_e <= 1e-6 of the smallest voxel size (in mm, the unit
+  of P^LM 1): a LOR that meets the image only within rounding (a corner
+  weight of 1e-12 where a boundary plane is crossed at an edge) carries no
+  dual step, where 1 / (P^LM 1)_e would make it arbitrarily large;
 * attenuation and normalisation (inside P, Section 1) are one factor per
   event's LOR, P' = diag(m) P; limited resolution is an image-space
   separable Gaussian B with a zero boundary, P = G B; the sensitivity g of
@@ -431,6 +435,22 @@ def _back_model(geom: Geometry, setup: "LMSetup", v: np.ndarray, ev: np.ndarray,
     return b if setup.fwhm is None else blur(b, setup.fwhm)
 
 
+P1_FLOOR = 1e-6  # of the smallest voxel size: below it a LOR misses the image
+
+
+def p1_floor(geom: "Geometry") -> float:
+    """The (P^LM 1)_e at or below which S_e = 0 (see the readings above)."""
+    return P1_FLOOR * float(min(geom.h))
+
+
+def step_S(P1: np.ndarray, gamma: float, rho: float, p1_min: float) -> np.ndarray:
+    """S_e = gamma rho / (P^LM 1)_e where (P^LM 1)_e > p1_min, else 0
+    (Eq. lm_stepsizes)."""
+    P1 = np.asarray(P1, dtype=np.float64)
+    on = P1 > p1_min
+    return np.where(on, gamma * rho / np.where(on, P1, 1.0), 0.0)
+
+
 def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float,
              rho: float, knorm: Optional[float] = None, xi: Optional[np.ndarray] = None,
              m: Optional[np.ndarray] = None, fwhm: Optional[Sequence[float]] = None) -> LMSetup:
@@ -446,7 +466,7 @@ def lm_setup(geom: Geometry, events, n_subsets: int, g: np.ndarray, gamma: float
     P1 = fwd(geom, np.ones(geom.shape) if fwhm is None else blur(np.ones(geom.shape), fwhm), ev)
     if m is not None:
         P1 = np.asarray(m, dtype=np.float64) * P1
-    S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
+    S = step_S(P1, gamma, rho, p1_floor(geom))
     kn = grad_norm(geom.shape) if (knorm is None or knorm <= 0) else float(knorm)
     T = rho / (2.0 * gamma * np.maximum(g, kn))
     return LMSetup(mu=mu, subsets=subsets, S=S, S_prior=gamma * rho / kn, T=T, g=g, knorm=kn, xi=xi,
@@ -524,16 +544,18 @@ def lm_spdhg(geom: Geometry, events, s: np.ndarray, g: np.ndarray, x0: np.ndarra
 def spdhg_sino(P: np.ndarray, d: np.ndarray, s: np.ndarray, x0: np.ndarray, bins_of_subset,
                seq, gamma: float, rho: float, beta: float, shape_zyx,
                T: Optional[np.ndarray] = None, knorm: Optional[float] = None,
-               xi: Optional[np.ndarray] = None):
+               xi: Optional[np.ndarray] = None, p1_min: float = 0.0):
     """P: [m, nvox] rows of the TOF sinogram operator; d: counts per bin;
     bins_of_subset: list of bin-index arrays; T: primal step, by default the
     preconditioned rule of Algorithm 1, T = min_k T_k with
     T_k = rho p_k / (gamma P_k^T 1) and T_prior = rho p_prior / (gamma ||K||),
-    p_k = 1/(2n), p_prior = 1/2; returns x after the updates."""
+    p_k = 1/(2n), p_prior = 1/2; p1_min: S is 0 for bins with P 1 at or
+    below it (p1_floor of the geometry, as in lm_setup); returns x after
+    the updates."""
     n = len(bins_of_subset)
     kn = grad_norm(shape_zyx) if (knorm is None or knorm <= 0) else float(knorm)
     P1 = P.sum(axis=1)
-    S = np.where(P1 > 0, gamma * rho / np.where(P1 > 0, P1, 1.0), 0.0)
+    S = step_S(P1, gamma, rho, p1_min)
     S_prior = gamma * rho / kn
     if T is None:
         Tk = [rho * (1.0 / (2 * n)) / (gamma * P[b].sum(axis=0)) for b in bins_of_subset]

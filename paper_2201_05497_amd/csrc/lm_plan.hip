@@ -188,10 +188,19 @@ __global__ void k_fill(float *p, float v, long long n) {
   if (i < n) p[i] = v;
 }
 
-// S_e = gamma rho / (P^LM 1)_e, 0 where the LOR misses the image.
-__global__ void k_step_S(const float *P1, float *S, float gr, long long n) {
+// S_e = gamma rho / (P^LM 1)_e (Eq. lm_stepsizes), 0 where the LOR misses
+// the image: (P^LM 1)_e <= p1_min, 1e-6 of the smallest voxel size (in mm,
+// the unit of P^LM 1), so that a LOR that meets the image only within
+// rounding (a corner weight of 1e-12 at an edge) carries no dual step.
+constexpr double kP1Floor = 1e-6;
+
+__global__ void k_step_S(const float *P1, float *S, float gr, float p1_min, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) S[i] = P1[i] > 0.0f ? gr / P1[i] : 0.0f;
+  if (i < n) S[i] = P1[i] > p1_min ? gr / P1[i] : 0.0f;
+}
+
+inline float p1_floor(const lm_geom &G) {
+  return (float)(kP1Floor * std::min(G.h[0], std::min(G.h[1], G.h[2])));
 }
 
 // T_j = rho / (2 gamma max(g_j, ||K||)).
@@ -499,7 +508,8 @@ int lm_plan_create(const lm_geom *G, const int16_t *ev, const float *s, int64_t 
   step(hipGetLastError(), "fill");
   if (rc == LM_OK && N > 0) rc = lmk::launch_fwd_rec(p->g, ones, p->rec, N, p->P1, st);
   if (N > 0) {
-    hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(gamma * rho), N);
+    hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(gamma * rho),
+                       p1_floor(p->G), N);
     step(hipGetLastError(), "step S");
   }
   // sensitivity (row-major, from the caller or lm_sens) into bricks, and T
@@ -716,7 +726,8 @@ int lm_plan_set_resolution(lm_plan *p, const double fwhm_vox[3], void *stream) {
       src = p->xb;
     }
     if (int rc = lmk::launch_fwd_rec(p->g, src, p->rec, N, p->P1, st)) return rc;
-    hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(p->gamma * p->rho), N);
+    hipLaunchKernelGGL(k_step_S, dim3(grid_for(N)), dim3(kBlock), 0, st, p->P1, p->S, (float)(p->gamma * p->rho),
+                       p1_floor(p->G), N);
     LM_TRY_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_fill, dim3(grid_for(E)), dim3(kBlock), 0, st, ones, 0.0f, E);
     LM_TRY_HIP(hipGetLastError());

@@ -203,7 +203,8 @@ def test_lm_equals_sinogram_one_subset_with_duplicates(orc):
     sb = np.full(len(bins), 0.05)
     # with one subset the sinogram step-size rule and the listmode rule coincide,
     # so the sinogram run derives T itself
-    x_sino = orc.spdhg_sino(P, d, sb, x0, [np.arange(len(bins))], seq, gamma, rho, beta, G.shape)
+    x_sino = orc.spdhg_sino(P, d, sb, x0, [np.arange(len(bins))], seq, gamma, rho, beta, G.shape,
+                            p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
 
 
@@ -223,7 +224,7 @@ def test_lm_equals_sinogram_subsets_unit_counts(orc):
     seq = lmsynth.subset_sequence(4, 0, 80, n)
     x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta)
     sb = np.full(len(bins), 0.05)
-    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape, T=su.T)
+    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape, T=su.T, p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
 
 
@@ -257,7 +258,7 @@ def test_primal_step_rule_with_n_subsets(orc):
     assert (seq < n).sum() > 10
     x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta)
     # the sinogram run derives T from its subsets (T=None)
-    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape)
+    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape, p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
 
 

@@ -60,7 +60,8 @@ def test_lm_with_blur_equals_sinogram(orc):
     gamma, rho, beta = 3 / x0.max(), 0.999, 0.05
     seq = lmsynth.subset_sequence(5, 0, 80, n)
     x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta, m=m_bin[boe], fwhm=fwhm)
-    x_sino = orc.spdhg_sino(Pm, d, np.full(len(bins), 0.05), x0, bos, seq, gamma, rho, beta, G.shape, T=su.T)
+    x_sino = orc.spdhg_sino(Pm, d, np.full(len(bins), 0.05), x0, bos, seq, gamma, rho, beta, G.shape, T=su.T,
+                            p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
     # the blur matters
     x_sharp, _, _ = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta, m=m_bin[boe])

@@ -66,7 +66,7 @@ def test_lm_equals_sinogram_dtv(orc):
     seq = lmsynth.subset_sequence(6, 0, 80, n)
     x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta, xi=xi)
     sb = np.full(len(bins), 0.05)
-    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape, T=su.T, xi=xi)
+    x_sino = orc.spdhg_sino(P, d, sb, x0, bos, seq, gamma, rho, beta, G.shape, T=su.T, xi=xi, p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
     # and DTV changes the iterates (the prior is not silently TV)
     x_tv, _, _ = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta)

@@ -27,7 +27,7 @@ def test_factors_one_subset_with_duplicates(orc):
     seq = lmsynth.subset_sequence(3, 0, 40, 1)
     x_lm, _, _ = orc.lm_spdhg(G, ev, s, g, x0, 1, seq, gamma, rho, beta, m=m_bin[boe])
     x_sino = orc.spdhg_sino(Pm, d, np.full(len(bins), 0.05), x0, [np.arange(len(bins))], seq, gamma, rho, beta,
-                            G.shape)
+                            G.shape, p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
     # the factors matter: without them the iterates differ
     x_plain, _, _ = orc.lm_spdhg(G, ev, s, g, x0, 1, seq, gamma, rho, beta)
@@ -45,5 +45,6 @@ def test_factors_subsets_unit_counts(orc):
     gamma, rho, beta = 3 / x0.max(), 0.999, 0.05
     seq = lmsynth.subset_sequence(4, 0, 80, n)
     x_lm, st, su = orc.lm_spdhg(G, ev, s, g, x0, n, seq, gamma, rho, beta, m=m_bin[boe])
-    x_sino = orc.spdhg_sino(Pm, d, np.full(len(bins), 0.05), x0, bos, seq, gamma, rho, beta, G.shape, T=su.T)
+    x_sino = orc.spdhg_sino(Pm, d, np.full(len(bins), 0.05), x0, bos, seq, gamma, rho, beta, G.shape, T=su.T,
+                            p1_min=orc.p1_floor(G))
     np.testing.assert_allclose(x_lm, x_sino, rtol=0, atol=1e-12 * np.abs(x_sino).max())
