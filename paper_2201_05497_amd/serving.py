@@ -25,7 +25,7 @@ import dataclasses
 import queue
 import threading
 import time
-from concurrent.futures import Future
+from concurrent.futures import CancelledError, Future
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -136,6 +136,7 @@ class _Active:
         self.pending: collections.deque = collections.deque()  # events of queued epochs
         self.bytes = 0
         self.error: Optional[BaseException] = None
+        self.cancel = False  # stop after the epochs in flight
 
 
 class Server:
@@ -146,8 +147,9 @@ class Server:
     plans' share).  max_active: most reconstructions admitted at once (being
     prepared or running).  epochs_in_flight: epochs queued ahead on each
     request's stream.  A request whose footprint alone exceeds the budget
-    fails with MemoryError.  ``close()`` waits for the admitted and queued
-    work.
+    fails with MemoryError.  ``cancel(future)`` drops a waiting request or
+    stops a running one after its epochs in flight, freeing its slot and
+    memory.  ``close()`` waits for the admitted and queued work.
 
     Two threads: the scheduler admits requests, issues epochs and completes
     results; a preparation thread uploads each admitted request's inputs
@@ -161,6 +163,8 @@ class Server:
         self.max_active = int(max_active)
         self.in_flight = max(1, int(epochs_in_flight))
         self._q: "queue.Queue[tuple]" = queue.Queue()
+        self._cancel_q: "queue.Queue[Future]" = queue.Queue()
+        self._cancelled: set = set()  # ids of futures whose requests are being cancelled
         self._prep_q: "queue.Queue[Optional[_Active]]" = queue.Queue()
         self._ready: "queue.Queue[_Active]" = queue.Queue()
         self._waiting: collections.deque = collections.deque()
@@ -191,6 +195,20 @@ class Server:
         self._q.put((req, fut, time.perf_counter()))
         return fut
 
+    def cancel(self, fut: Future) -> bool:
+        """Cancels a request.  A waiting one is dropped (``fut.cancelled()``
+        is then true).  A running one, being prepared or with epochs on the
+        device, stops after the epochs already queued: its plan and memory
+        are released and ``fut.result()`` raises CancelledError (a request
+        that completes before the scheduler acts keeps its result).  Returns
+        False if the request had already finished."""
+        if fut.done():
+            return False
+        if fut.cancel():
+            return True
+        self._cancel_q.put(fut)
+        return True
+
     def close(self, wait: bool = True) -> None:
         self._stop = True
         if wait:
@@ -212,6 +230,7 @@ class Server:
             torch.cuda.set_device(self.device)
             while True:
                 self._drain_queue()
+                self._drain_cancels()
                 self._collect_ready()
                 self._admit()
                 progressed = self._tick()
@@ -237,6 +256,26 @@ class Server:
             except queue.Empty:
                 return
             self._waiting.append((req, fut, t))
+
+    def _drain_cancels(self):
+        while True:
+            try:
+                fut = self._cancel_q.get_nowait()
+            except queue.Empty:
+                return
+            self._cancelled.add(id(fut))
+            for a in self._active:
+                if a.fut is fut:
+                    a.cancel = True
+
+    def _finish_cancelled(self, a: _Active):
+        """Frees a cancelled request once its queued work is done."""
+        self._cancelled.discard(id(a.fut))
+        if a.stream is not None:
+            a.stream.synchronize()
+        self._release(a)
+        if not a.fut.done():
+            a.fut.set_exception(CancelledError(f"request {a.req.name} cancelled"))
 
     def _admit(self):
         while self._waiting and len(self._active) + self._preparing < self.max_active:
@@ -298,16 +337,20 @@ class Server:
                 return
             self._preparing -= 1
             if a.error is not None:
+                self._cancelled.discard(id(a.fut))
                 self._release(a)
                 if not a.fut.done():
                     a.fut.set_exception(a.error)
+                continue
+            if id(a.fut) in self._cancelled:  # cancelled while being prepared
+                self._finish_cancelled(a)
                 continue
             self._active.append(a)
 
     def _tick(self) -> bool:
         progressed = False
         for a in self._active:
-            if a.fut.cancelled():
+            if a.fut.cancelled() or a.cancel:
                 continue
             while a.pending and a.pending[0].query():
                 a.pending.popleft()
@@ -334,6 +377,13 @@ class Server:
         keep = []
         done_any = False
         for a in self._active:
+            if a.cancel:
+                if all(e.query() for e in a.pending):
+                    self._finish_cancelled(a)
+                    done_any = True
+                else:
+                    keep.append(a)
+                continue
             done = a.issued >= len(a.seq) and all(e.query() for e in a.pending)
             if a.fut.cancelled():
                 done = True

@@ -1,7 +1,10 @@
 """The continuous-batching server: every served reconstruction equals the
 same reconstruction run alone by the plain solver (float32 atomics aside),
 admission never exceeds the HBM budget, oversized requests fail cleanly and
-waiting requests can be cancelled."""
+waiting and running requests can be cancelled."""
+import time
+from concurrent.futures import CancelledError
+
 import numpy as np
 import pytest
 import torch
@@ -109,3 +112,34 @@ def test_failed_preparation_fails_alone(P):
             fb.result(timeout=120)
     assert [r.name for r in res] == [r.name for r in reqs]
     assert srv._used == 0
+
+
+def test_running_request_can_be_cancelled(P):
+    """A request cancelled while its epochs run stops, raises CancelledError
+    and frees its slot and memory; a request admitted beside it, and one
+    that needs the freed slot, complete and equal their plain-solver runs."""
+    S = P_serving()
+    reqs, geoms = _requests(P, count=3, seed=34)
+    r0 = reqs[0]
+    long_req = S.Request(r0.geom, r0.events, r0.s, r0.x0, n_subsets=8, epochs=2000, seq_seed=7, name="long")
+    with S.Server(hbm_budget=8 << 30, max_active=2) as srv:
+        for g in geoms:
+            srv.warm(g)
+        f_long = srv.submit(long_req)
+        f1 = srv.submit(reqs[1])
+        f2 = srv.submit(reqs[2])  # waits for a slot
+        t0 = time.perf_counter()
+        while not f_long.running() and time.perf_counter() - t0 < 60:
+            time.sleep(0.01)
+        time.sleep(0.2)  # let it prepare and queue epochs
+        assert f_long.running() and not f_long.done()
+        assert srv.cancel(f_long)
+        with pytest.raises(CancelledError):
+            f_long.result(timeout=120)
+        res = [f1.result(timeout=120), f2.result(timeout=120)]
+        assert not srv.cancel(f1)  # finished: nothing to cancel
+    assert srv._used == 0
+    assert sorted(r.name for r in srv.results) == sorted(r.name for r in reqs[1:])
+    worst = max(img_err(a.x, S.solve(r).astype(np.float64)) for a, r in zip(res, reqs[1:]))
+    report("cancel running", worst=worst, elapsed=time.perf_counter() - t0)
+    assert worst <= 1e-4
