@@ -14,9 +14,12 @@ region.
 
 It prints one JSON line: value = events forward- and back-projected per
 second over the timed epochs, the roofline of the dominant kernel (the
-fused data update, on its algorithmic bytes) and its binding resource (its
-FP32 atomic requests per second against a ceiling calibrated in the same
-run), the FP64 oracle timed on a bounded sample of the same workload on the
+data update by image tile with the z / zbar / primal step fused into it,
+on its algorithmic bytes, next to its HBM traffic measured with rocprofv3)
+and its binding resource (its VALU instructions per second, from counts
+measured with rocprofv3, against the chip's issue rate: 256 CUs x 4 SIMDs
+x 2.4 GHz / 4 cycles per wavefront instruction), the FP64 oracle timed on
+a bounded sample of the same workload on the
 host (cpu_baseline), the same reconstruction continued with the DTV prior
 (ms per epoch and per prior update), ms per epoch with the full forward
 model (per-LOR factors and a Gaussian resolution model), the warm start of the same workload (one listmode
@@ -33,10 +36,14 @@ with p50/p99 latency and events/s next to the one-frame-at-a-time solver on
 the same arrivals, and the same 64 requests submitted at once (burst
 makespan against the solver's total).
 
+The default run ends with the long frame (below); ``--only-epoch`` runs
+the 1e7-event epoch leg alone (profiler runs).
+
 ``--workload large``: the same scanner with a 300x300x96 image of 1.75 x
 1.75 x 2.6 mm voxels and 5e8 events presented sorted by dominant axis: one
-lm_fwd + lm_back pass over all events per step (lm_back takes its
-by-line path for such a list), then one LM-SPDHG epoch.
+lm_fwd + lm_back pass over all events per step (both take their paths by
+transaxial line after a counting sort of the list on the GPU), then one
+LM-SPDHG epoch.
 """
 from __future__ import annotations
 
@@ -52,6 +59,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# VALU issue rate: 256 CUs x 4 SIMDs x 2.4 GHz, one wavefront instruction
+# per 4 cycles on a 16-lane SIMD
+VALU_PEAK_INSTR = 256 * 4 * 2.4e9 / 4
 N_SUB = 224
 BETA = 0.03
 RHO = 0.999
@@ -93,11 +103,11 @@ WARM_DENOISE = 20               # 20 accelerated PDHG steps per denoising
 # traffic below was measured.
 CSRC = os.path.join(HERE, "paper_2201_05497_amd", "csrc")
 KERNEL_SOURCES = {
-    "data_update": ["lm_project.hip", "lm_device.hpp"],
+    "data_update": ["lm_tiles.hip", "lm_tiles.hpp", "lm_project.hip", "lm_device.hpp"],
     "dual_image": ["lm_image.hip"],
     "tv": ["lm_image.hip", "lm_device.hpp"],
     "primal": ["lm_image.hip"],
-    "fwd": ["lm_project.hip", "lm_device.hpp"],
+    "fwd": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip"],
     "back": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip"],
 }
 
@@ -106,26 +116,30 @@ KERNEL_SOURCES = {
 # plain copy of known size in the same run; `sources` is the digest of the
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
-    "data_update": {"fetch_bytes": 104902058, "write_bytes": 98294700, "sources": "5938545011bd2338",
+    # the data update by image tile: phase 1 (k_tile_fwd) + phase 2 (k_tile_back)
+    "data_update": {"fetch_bytes": 220300000, "write_bytes": 70100000, "sources": "f90fd5f179e692f5",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106291905, "write_bytes": 76854145, "sources": "9b6e39d3be0a4650",
+    "tv": {"fetch_bytes": 106200000, "write_bytes": 76900000, "sources": "bbd499960c963172",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     "dual_image": {"fetch_bytes": 61408650, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
+    # one lm_fwd / lm_back call over the 5e8-event long frame: the counting
+    # sort and the line kernels
+    "fwd": {"fetch_bytes": 100730000000, "write_bytes": 57120000000, "sources": "8cef74701e63d03e",
+        "profile": "profiles/pass_3d_300x300x96_counters.txt"},
+    "back": {"fetch_bytes": 92080000000, "write_bytes": 117320000000, "sources": "8cef74701e63d03e",
+        "profile": "profiles/pass_3d_300x300x96_counters.txt"},
 }
 
 
-# FP32 atomic requests per event of the kernels that scatter, measured with
-# rocprofv3 --pmc TCC_ATOMIC_sum (all of them are executed beyond the L2:
-# TCC_EA0_ATOMIC_sum reads the same), with the digest of the kernel's
-# sources at the time.
-PMC_ATOMICS: dict = {
-    "data_update": {"requests_per_event": 47.29, "sources": "5938545011bd2338",
+# VALU wavefront instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU),
+# with the digest of the kernel's sources at the time.
+PMC_VALU: dict = {
+    "data_update": {"instr_per_launch": 50900000, "sources": "f90fd5f179e692f5",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
 }
 
-# Number of random positions of the atomic-rate calibration.
-ATOMIC_PROBE_N = 1 << 26
+
 
 
 def log(msg: str) -> None:
@@ -157,54 +171,19 @@ def traffic(cls: str):
     return int(t["fetch_bytes"] + t["write_bytes"])
 
 
-def atomic_requests_per_event(cls: str):
-    """Measured atomic requests per event of a kernel class, or None when
-    none were measured or the kernel's sources changed since."""
-    t = PMC_ATOMICS.get(cls)
-    if t is None or t["sources"] != source_digest(cls):
-        return None
-    return float(t["requests_per_event"])
-
-
-def calibrate_atomics(torch, dev, n_img: int = 3_840_000, reps: int = 10) -> float:
-    """Ceiling of the FP32 atomic request rate: index_add_ of ones at
-    ATOMIC_PROBE_N uniformly random positions of an image of n_img floats.
-    The 64 lanes of an instruction then almost never share a 64-byte
-    sector, so every lane-atomic is a request of its own; requests/s."""
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(0)
-    idx = torch.randint(0, n_img, (ATOMIC_PROBE_N,), generator=gen, device=dev, dtype=torch.int64)
-    src = torch.ones(ATOMIC_PROBE_N, device=dev)
-    buf = torch.zeros(n_img, device=dev)
-    for _ in range(2):
-        buf.index_add_(0, idx, src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        buf.index_add_(0, idx, src)
-    e1.record()
-    torch.cuda.synchronize()
-    rate = ATOMIC_PROBE_N * reps / (e0.elapsed_time(e1) * 1e-3)
-    del idx, src, buf
-    return rate
-
-
-def binding(cls: str, events_per_launch: float, us_per_launch: float, ceiling: float) -> dict:
-    """The resource that bounds a scattering kernel: its atomic requests
-    per second (measured requests per event x events per launch / live
-    launch duration) against the calibrated ceiling."""
-    out = {"kernel": cls, "resource": "FP32 atomic requests executed beyond the L2 (one per 64-byte sector "
-                                      "that lanes of an instruction share)",
-           "unit": "requests/s", "ceiling": float(f"{ceiling:.4g}"),
-           "ceiling_probe": f"torch index_add_ of {ATOMIC_PROBE_N} ones at random positions of 3.84e6 floats",
-           "achieved": None, "frac": None, "requests_per_launch": None, "sources": source_digest(cls)}
-    r = atomic_requests_per_event(cls)
-    if r is not None:
-        req = r * events_per_launch
-        achieved = req / (us_per_launch * 1e-6)
-        out.update(achieved=float(f"{achieved:.4g}"), frac=round(achieved / ceiling, 3),
-                   requests_per_launch=int(req))
+def binding(cls: str, us_per_launch: float) -> dict:
+    """The resource that bounds the data update by tile (it issues no global
+    atomics; its phase 2 is bound by its arithmetic): measured VALU
+    wavefront instructions per launch / live launch duration against the
+    chip's issue rate."""
+    out = {"kernel": cls, "resource": "VALU wavefront instructions", "unit": "instructions/s",
+           "ceiling": VALU_PEAK_INSTR, "ceiling_derivation": "256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles",
+           "achieved": None, "frac": None, "instr_per_launch": None, "sources": source_digest(cls)}
+    t = PMC_VALU.get(cls)
+    if t is not None and t["sources"] == source_digest(cls):
+        achieved = t["instr_per_launch"] / (us_per_launch * 1e-6)
+        out.update(achieved=float(f"{achieved:.4g}"), frac=round(achieved / VALU_PEAK_INSTR, 3),
+                   instr_per_launch=t["instr_per_launch"])
     return out
 
 
@@ -377,11 +356,15 @@ def epoch_leg(args, torch, P, lmsynth):
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         if dom == "data_update":
             bpl = BYTES_PER_EVENT * n_proj / n_data
+            if "dual_image" not in kernels:
+                # the tile path fuses the z / zbar / primal step of every
+                # voxel into the data update
+                bpl += BYTES_PER_VOXEL["dual_image"] * nvox
         else:
             bpl = BYTES_PER_VOXEL[dom] * nvox
         roof = roofline(dom, bpl, kernels[dom]["us_avg"])
         if dom == "data_update":
-            bind = binding(dom, n_proj / n_data, kernels[dom]["us_avg"], calibrate_atomics(torch, dev))
+            bind = binding(dom, kernels[dom]["us_avg"])
 
     out = {
         "metric": "TOF LM fwd+back events/s + %HBM peak; LM-SPDHG s/epoch; served p50/p99",
@@ -871,6 +854,9 @@ def main() -> int:
     ap.add_argument("--no-large", action="store_true", help="skip the 5e8-event long frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--only-epoch", action="store_true",
+                    help="the 1e7-event epoch leg alone (for profiler runs): no warm start, 2D, convergence, "
+                         "autograd, serving or long-frame legs")
     ap.add_argument("--timing-every", type=int, default=8,
                     help="bracket every k-th launch of each kernel class with HIP events (0: no per-kernel timing)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -903,11 +889,12 @@ def main() -> int:
             log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
     else:
         out, p, G, g = epoch_leg(args, torch, P, lmsynth)
-        out["warm_start"] = warm_start_leg(torch, P, G, g, p)
-        out["epoch_2d"] = leg_2d(torch, P, lmsynth)
-        out["convergence"] = convergence_leg(torch, P, lmsynth)
-        out["autograd"] = autograd_leg(torch, P, lmsynth)
-        if not args.no_serve:
+        if not args.only_epoch:
+            out["warm_start"] = warm_start_leg(torch, P, G, g, p)
+            out["epoch_2d"] = leg_2d(torch, P, lmsynth)
+            out["convergence"] = convergence_leg(torch, P, lmsynth)
+            out["autograd"] = autograd_leg(torch, P, lmsynth)
+        if not args.no_serve and not args.only_epoch:
             out["served"] = serving_leg(torch, P, lmsynth, G, g, p)
         cpu = None
         if not args.no_cpu_baseline:
@@ -918,7 +905,7 @@ def main() -> int:
             log(f"cpu baseline: {cpu['value']:.3e} events/s ({time.perf_counter() - t0:.1f} s)")
         del G, g, p
         torch.cuda.empty_cache()
-        if not args.no_large:
+        if not args.no_large and not args.only_epoch:
             # the long frame: a few passes whatever --steps says, to keep the run short
             large, pl = large_leg(args, torch, P, lmsynth, passes=min(args.steps, 5), warmup=min(args.warmup, 2))
             if not args.no_cpu_baseline:

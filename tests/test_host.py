@@ -80,19 +80,20 @@ def test_bench_traffic_guarded_by_source_digest(monkeypatch):
 
 
 def test_bench_binding_guarded_by_source_digest(monkeypatch):
-    """The atomic request rate is reported only while the kernel's sources
-    are the ones its requests per event were measured on."""
+    """The VALU instruction rate of the data update is reported only while
+    the kernel's sources are the ones its instructions were counted on."""
     sys.path.insert(0, ROOT)
     import importlib
     bench = importlib.import_module("bench")
     dig = bench.source_digest("data_update")
-    monkeypatch.setitem(bench.PMC_ATOMICS, "data_update", {"requests_per_event": 50.0, "sources": dig})
-    b = bench.binding("data_update", 40_000, 100.0, 2.0e10)
-    assert b["requests_per_launch"] == 2_000_000
-    assert b["achieved"] == pytest.approx(2.0e10) and b["frac"] == pytest.approx(1.0)
-    monkeypatch.setitem(bench.PMC_ATOMICS, "data_update", {"requests_per_event": 50.0, "sources": "0" * 16})
-    b = bench.binding("data_update", 40_000, 100.0, 2.0e10)
-    assert b["achieved"] is None and b["frac"] is None and b["ceiling"] == 2.0e10
+    peak = bench.VALU_PEAK_INSTR
+    assert peak == pytest.approx(6.144e11)
+    monkeypatch.setitem(bench.PMC_VALU, "data_update", {"instr_per_launch": int(peak * 50e-6), "sources": dig})
+    b = bench.binding("data_update", 100.0)
+    assert b["achieved"] == pytest.approx(peak / 2, rel=1e-3) and b["frac"] == pytest.approx(0.5, abs=1e-3)
+    monkeypatch.setitem(bench.PMC_VALU, "data_update", {"instr_per_launch": 1, "sources": "0" * 16})
+    b = bench.binding("data_update", 100.0)
+    assert b["achieved"] is None and b["frac"] is None and b["ceiling"] == peak
 
 
 def test_product_package_never_imports_the_oracle():
