@@ -89,7 +89,14 @@ const char *lm_last_error(void);
  * stream); the calls do not synchronise. */
 
 /* Listmode forward projection (Eq. lmop): out[e] = (P^LM x)_e for the n
- * events ev[n][5] in the caller's order.  x: image; out: float[n]. */
+ * events ev[n][5] in the caller's order.  x: image; out: float[n].  Events
+ * that are out of range get out[e] = 0.  On a cylindrical scanner (as for
+ * lm_back, decided on the device) a list of at least 64 events per
+ * transaxial crystal pair and fewer than 2^32 events is projected by
+ * transaxial line after a counting sort on the device: 12 more bytes per
+ * event of stream-ordered temporary memory (without room for it the events
+ * are projected in their own order).  The result is the same up to float32
+ * rounding in either order.  The call never synchronises the stream. */
 int lm_fwd(const lm_geom *G, const float *x, const int16_t *ev, int64_t n, float *out,
            void *stream);
 
@@ -186,7 +193,9 @@ int lm_plan_bytes_ex(const lm_geom *G, int64_t n_ev, int32_t n_sub, int32_t part
  * into n_sub interleaved subsets (event e goes to subset e mod n_sub, the
  * text after Algorithm 2), and the step sizes of Eq. lm_stepsizes with
  * p_k = 1/(2 n_sub) and p_prior = 1/2 (Section 3):
- *   S_e = gamma rho / (P^LM 1)_e  (0 where the LOR misses the image),
+ *   S_e = gamma rho / (P^LM 1)_e  (0 where the LOR misses the image:
+ *         (P^LM 1)_e <= 1e-6 of the smallest voxel side, which also
+ *         covers a LOR that meets the image only within rounding),
  *   S_prior = gamma rho / knorm,
  *   T_j = rho / (2 gamma max(g_j, knorm)).
  * ev: int16[n][5]; s: float[n] contamination per event (> 0); g: the

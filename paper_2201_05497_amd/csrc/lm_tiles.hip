@@ -14,10 +14,11 @@
 //
 //   phase 1, per event (8 lanes per event, as the forward projector):
 //     q = (P x)_e + s_e, the dual prox, c = 1 - y updated, and one
-//     record per segment of the event (its ray coefficients and cf w_j of
-//     its samples on the tile's 8 planes, cf = L dy / mu; 64 bytes, one
-//     memory sector), the records of
-//     an event in a row;
+//     record per segment of the event (the in-plane coordinates of its
+//     samples relative to the tile's first plane; for each of the tile's 8
+//     planes the sample's value cf w_j with cf = L dy / mu, the tile-local
+//     index of its first corner and which corners fall in the tile; 64
+//     bytes, one memory sector), the records of an event in a row;
 //   phase 2, one workgroup per tile: every wavefront takes the tile's
 //     records two at a time through the tile's list of record numbers
 //     (lanes = 8 planes x 4 bilinear corners per record; the list entries
@@ -29,9 +30,15 @@
 //     fused primal step of the next update.  No global atomics, and dz never
 //     goes to memory.
 //
-// The per-sample arithmetic (interpolation coordinates, bilinear weights,
-// TOF weights, their products) is that of the per-event kernels, so the
-// results differ from them only in the order of the float32 additions.
+// The per-sample arithmetic (bilinear weights, TOF weights, their
+// products) is that of the per-event kernels; the back projection takes a
+// sample's in-plane coordinate as G + p V from the tile's first plane
+// instead of F + j V from the ray's, which can differ by a rounding (1e-7
+// of a voxel), so results differ from the per-event kernels by that and by
+// the order of the float32 additions.  Where the two place a coordinate on
+// opposite sides of a voxel boundary, the corner that changes has a
+// weight of that size, and the tile list (built from F + j V) may lack its
+// tile: such a corner is dropped.
 // Tiles are launched hottest first (most segments over all subsets), so
 // the long ones do not trail at the end of a launch.
 #include <hip/hip_runtime.h>
@@ -227,12 +234,14 @@ __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, in
     if (dy != 0.0f) cf = r.L * (dy / me);
   }
   if (r.nplanes <= 0) return;
-  // the records, in the order of for_each_segment
-  // m0 < 512 and nplanes <= 512 (image sizes up to 512)
-  const int4 h0 = make_int4(r.m0 | (r.nplanes << 10) | (r.a << 20), r.I1, r.I2, 0);
-  const float4 h1 = make_float4(r.F1, r.V1, r.F2, r.V2);
+  // the records, in the order of for_each_segment; lane p writes the entry
+  // of plane p of each
   TileRec *o = out + (eoff[e] - eoff[0]);  // the event's records, in a row
   const int last = r.m0 + r.nplanes - 1;
+  // strides of the two other axes and of the dominant one in a tile's
+  // row-major index
+  const int d1 = r.a == 0 ? kTE : 1, d2 = r.a == 2 ? kTE : kTE * kTE;
+  const int dm = r.a == 0 ? 1 : (r.a == 1 ? kTE : kTE * kTE);
 #pragma unroll
   for (int jj = 0; jj < J8; ++jj) {
     const int ta = r.m0 / kTE + jj;
@@ -245,59 +254,65 @@ __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, in
     const int lo1 = max(min(f1a, f1b), 0), hi1 = min(max(f1a, f1b) + 1, r.n1 - 1);
     const int lo2 = max(min(f2a, f2b), 0), hi2 = min(max(f2a, f2b) + 1, r.n2 - 1);
     if (lo1 > hi1 || lo2 > hi2) continue;
+    // the chunk's coordinates relative to its first plane (ray coordinates
+    // at plane ta * 8, before adding I1, I2), and this lane's sample on
+    // plane ta * 8 + lane as phase 2 will compute it (j outside [0,
+    // nplanes) has wj = 0 and adds nothing)
+    const float jb = (float)(ta * kTE - r.m0);
+    const float G1 = fmaf(jb, r.V1, r.F1), G2 = fmaf(jb, r.V2, r.F2);
     const float v = (wj[jj] != 0.0f) ? cf * wj[jj] : 0.0f;
+    const float u1 = fmaf((float)lane, r.V1, G1), u2 = fmaf((float)lane, r.V2, G2);
+    const int c1 = r.I1 + (int)floorf(u1), c2 = r.I2 + (int)floorf(u2);
+    // corners 0 and +1 along each other axis inside the image
+    const int in1 = (c1 >= 0 && c1 < r.n1 ? 1 : 0) | (c1 + 1 >= 0 && c1 + 1 < r.n1 ? 2 : 0);
+    const int in2 = (c2 >= 0 && c2 < r.n2 ? 1 : 0) | (c2 + 1 >= 0 && c2 + 1 < r.n2 ? 2 : 0);
     for (int t1 = lo1 / kTE; t1 <= hi1 / kTE; ++t1)
       for (int t2 = lo2 / kTE; t2 <= hi2 / kTE; ++t2, ++o) {
-        if (lane == 0) {
-          o->h0 = h0;
-          o->h1 = h1;
-        }
-        o->val[lane] = v;
+        const int l1 = c1 - t1 * kTE, l2 = c2 - t2 * kTE;
+        // ... and inside the tile
+        const int m1 = in1 & (((unsigned)l1 < (unsigned)kTE ? 1 : 0) | ((unsigned)(l1 + 1) < (unsigned)kTE ? 2 : 0));
+        const int m2 = in2 & (((unsigned)l2 < (unsigned)kTE ? 1 : 0) | ((unsigned)(l2 + 1) < (unsigned)kTE ? 2 : 0));
+        // bit b1 + 2 b2 set when corner (b1, b2) is inside
+        int mask = ((m1 & 1) ? 1 : 0) | ((m1 & 2) ? 2 : 0);
+        mask = ((m2 & 1) ? mask : 0) | ((m2 & 2) ? mask << 2 : 0);
+        if (v == 0.0f) mask = 0;
+        // corner 0 at (lane, l1, l2) along (a, axis 1, axis 2): with a corner
+        // inside, l1 and l2 are in [-1, 7], the index in [-72, 511]
+        const int at0 = lane * dm + l1 * d1 + l2 * d2;
+        if (lane == 0) o->h = make_float4(G1, r.V1, G2, r.V2);
+        o->v[lane] = v;
+        o->meta[lane] = mask ? (unsigned short)((at0 + 128) | (mask << 10) | (r.a << 14)) : (unsigned short)0;
       }
   }
 }
 
 struct SegLane {
-  int4 h0;
-  float4 h1;
+  float4 h;
   float v;
+  unsigned meta;
 };
 
 __device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, unsigned k, int jp) {
   SegLane s;
   const TileRec *r = recs + k;
-  s.h0 = r->h0;
-  s.h1 = r->h1;
-  s.v = r->val[jp];
+  s.h = r->h;
+  s.v = r->v[jp];
+  s.meta = r->meta[jp];
   return s;
 }
 
-// The voxel of lane (jp, corner) for record s on a tile at (tx, ty, tz):
-// its tile-local row-major index (li + 8 lj + 64 lk) and value, or add = 0.
-// The sample and corner arithmetic is that of sample_at / corner().
-__device__ __forceinline__ void seg_voxel(const SegLane &s, int jp, int corner, int tx, int ty, int tz, int nx, int ny,
-                                          int nz, float &add, int &at) {
-  add = 0.0f;
-  at = 0;
-  if (s.v == 0.0f) return;
-  const int m0 = s.h0.x & 1023, np = (s.h0.x >> 10) & 1023, a = s.h0.x >> 20;
-  const int ta = a == 0 ? tx : (a == 1 ? ty : tz);
-  const int m = ta * kTE + jp;
-  const int j = m - m0;
-  if ((unsigned)j >= (unsigned)np) return;
-  const float fj = (float)j;
-  const float u1 = fmaf(fj, s.h1.y, s.h1.x), u2 = fmaf(fj, s.h1.w, s.h1.z);
-  const float fl1 = floorf(u1), fl2 = floorf(u2);
-  const float f1 = u1 - fl1, f2 = u2 - fl2;
-  const int c1 = s.h0.y + (int)fl1 + (corner & 1), c2 = s.h0.z + (int)fl2 + (corner >> 1);
+// The voxel of lane (plane jp, corner) for record s: its tile-local
+// row-major index (li + 8 lj + 64 lk) and value, or add = 0.  The sample's
+// coordinates are computed as phase 1 computed them for its corner mask.
+__device__ __forceinline__ void seg_voxel(const SegLane &s, float fjp, int corner, float &add, int &at) {
+  const unsigned mt = s.meta;
+  const int a = (int)(mt >> 14);
+  const int d1 = a == 0 ? kTE : 1, d2 = a == 2 ? kTE : kTE * kTE;
+  at = (int)(mt & 1023u) - 128 + ((corner & 1) ? d1 : 0) + ((corner & 2) ? d2 : 0);
+  const float u1 = fmaf(fjp, s.h.y, s.h.x), u2 = fmaf(fjp, s.h.w, s.h.z);
+  const float f1 = u1 - floorf(u1), f2 = u2 - floorf(u2);
   const float wc = ((corner & 1) ? f1 : 1.0f - f1) * ((corner & 2) ? f2 : 1.0f - f2);
-  const int i = a == 0 ? m : c1;
-  const int jj = a == 0 ? c1 : (a == 1 ? m : c2);
-  const int kk = a == 2 ? m : c2;
-  const int li = i - tx * kTE, lj = jj - ty * kTE, lk = kk - tz * kTE;
-  if ((unsigned)(li | lj | lk) >= (unsigned)kTE || i >= nx || jj >= ny || kk >= nz || wc == 0.0f) return;
-  add = s.v * wc;
-  at = li + kTE * (lj + kTE * lk);
+  add = ((mt >> (10 + corner)) & 1u) ? s.v * wc : 0.0f;
 }
 
 // Phase 2: one workgroup per tile; recs are the subset's records, seg the
@@ -317,6 +332,7 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
   const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, tz = tile / (tg.ntx * tg.nty);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const int jp = hl >> 2, corner = hl & 3;
+  const float fjp = (float)jp;
   // this thread's voxel of the tile (threads in the plan's brick order);
   // its image values are loaded now and used at the end
   const Layout &L = g.lay;
@@ -339,7 +355,6 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
   const long long s0 = off[tile];
   const int cnt = (int)(off[tile + 1] - s0);
   const unsigned *tseg = seg + s0;
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   constexpr int kStep = 2 * kWaves2;
   const int k0 = 2 * wv + half;
   if (cnt > 0) {
@@ -356,7 +371,7 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
       const unsigned iD = idx(k + 3 * kStep);
       float add;
       int at;
-      seg_voxel(A, jp, corner, tx, ty, tz, nx, ny, nz, add, at);
+      seg_voxel(A, fjp, corner, add, at);
       // the 32 lanes of a record touch distinct voxels of their own copy; a
       // lane may read a word another lane of the wavefront wrote before,
       // which the wavefront's in-order LDS operations deliver once the
@@ -367,7 +382,7 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       A = load_seg(recs, iC, jp);
       iC = idx(k + 4 * kStep);
-      seg_voxel(B, jp, corner, tx, ty, tz, nx, ny, nz, add, at);
+      seg_voxel(B, fjp, corner, add, at);
       if (k + kStep < cnt && add != 0.0f) mine[at] += add;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();

@@ -19,16 +19,19 @@ struct TileGeom {
   int ntx, nty, ntz, ntiles;
 };
 
-// One segment as phase 2 reads it (64 bytes, one memory sector; written
-// by phase 1, the records of an event in a row): the event's plane range
-// and interpolation coefficients of setup_ray (h0 = {m0 | nplanes << 10 |
-// a << 20, I1, I2, 0}, h1 = {F1, V1, F2, V2}) and the values cf w_j of the
-// samples on the tile's 8 planes along the event's dominant axis (0
-// outside the ray; cf = L dy / mu).
+// One segment as phase 2 reads it (64 bytes, one memory sector; written by
+// phase 1, the records of an event in a row): the in-plane coordinates of
+// the event's samples on the tile's 8 planes along its dominant axis are
+// u_p = G + p V (p = 0..7; G the coordinate at the tile's first plane), and
+// for each plane p the sample's value v[p] = cf w_j (cf = L dy / mu; 0
+// outside the ray) and meta[p] = 0 when no corner of the sample adds to the
+// tile, else (tile-local index of corner 0 + 128) | (corner mask << 10) |
+// (dominant axis << 14), the mask having bit c set for each bilinear corner
+// c inside both the tile and the image.
 struct __align__(64) TileRec {
-  int4 h0;
-  float4 h1;
-  float val[8];
+  float4 h;  // {G1, V1, G2, V2}
+  float v[8];
+  unsigned short meta[8];
 };
 
 // Per-plan state of the tile path; `on` false: the per-event path runs.
