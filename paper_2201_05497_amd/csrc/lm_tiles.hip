@@ -103,34 +103,52 @@ __device__ __forceinline__ void for_each_segment(const Ray &r, const TileGeom &t
   }
 }
 
-// Segments of one subset's events: per (subset, tile) and per event.
-__global__ __launch_bounds__(256) void k_tile_count(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long n,
-                                                    unsigned *cnt, unsigned *ecnt) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+// The subset stored at position e: the last i with sub[i] <= e (sub: the
+// nsub + 1 first positions of the subsets, non-decreasing, sub[nsub] = n).
+__device__ __forceinline__ int subset_at(const long long *sub, int nsub, long long e) {
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sub[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Segments of every stored event, all subsets in one launch: per (subset,
+// tile) and per event.
+__global__ __launch_bounds__(256) void k_tile_count(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long e0,
+                                                    long long n, const long long *sub, int nsub, unsigned *cnt,
+                                                    unsigned *ecnt) {
+  const long long e = e0 + (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
+  unsigned *c = cnt + (long long)subset_at(sub, nsub, e) * tg.ntiles;
   const int4 rc = rec[e];
   const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
   unsigned q = 0;
   for_each_segment(r, tg, [&](int t) {
-    atomicAdd(cnt + t, 1u);
+    atomicAdd(c + t, 1u);
     ++q;
   });
   ecnt[e] = q;
 }
 
-// Lists, per tile, the records of the subset's segments that fall in it
-// (rank from an atomic counter: the order inside a tile is not fixed).
-// Records are numbered in event order from the subset's first event
-// (eoff[0]): event e's q-th segment is record eoff[e] - eoff[0] + q.
-__global__ __launch_bounds__(256) void k_tile_place(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long n,
-                                                    const long long *off, unsigned *fill,
-                                                    const unsigned long long *eoff, unsigned *seg) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+// Lists, per (subset, tile), the records of the subset's segments that fall
+// in the tile (rank from an atomic counter: the order inside a tile is not
+// fixed).  Records are numbered in event order from the subset's first
+// event: event e's q-th segment is record eoff[e] - eoff[sub[i]] + q.
+__global__ __launch_bounds__(256) void k_tile_place(GeomDev g, TileGeom tg, int maxp, const int4 *rec, long long e0,
+                                                    long long n, const long long *sub, int nsub, const long long *off,
+                                                    unsigned *fill, const unsigned long long *eoff, unsigned *seg) {
+  const long long e = e0 + (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
+  const int i = subset_at(sub, nsub, e);
+  const long long *o = off + (long long)i * tg.ntiles;
+  unsigned *f = fill + (long long)i * tg.ntiles;
   const int4 rc = rec[e];
   const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
-  unsigned q = (unsigned)(eoff[e] - eoff[0]);
-  for_each_segment(r, tg, [&](int t) { seg[off[t] + atomicAdd(fill + t, 1u)] = q++; });
+  unsigned q = (unsigned)(eoff[e] - eoff[sub[i]]);
+  for_each_segment(r, tg, [&](int t) { seg[o[t] + atomicAdd(f + t, 1u)] = q++; });
 }
 
 // Exclusive prefix sum of cnt[0 .. n) into off[0 .. n] (64-bit); one block
@@ -413,6 +431,10 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
 
 inline unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// events per launch of the per-event set-up kernels (a dispatch covers at
+// most 2^30 work-items)
+constexpr long long kChunk = 1LL << 28;
+
 }  // namespace
 
 namespace lmk {
@@ -477,9 +499,10 @@ int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, 
   const int maxp = lmh::max_planes(g, W_BIN);
   const long long nbin = (long long)nsub * tg.ntiles;
   const long long nblk = (N + kScanB - 1) / kScanB;
-  // temporaries: counts per (subset, tile) and per event, block sums
+  // temporaries: counts per (subset, tile) and per event, block sums, the
+  // subsets' first positions
   unsigned *cnt = nullptr, *ecnt = nullptr, *bsum = nullptr;
-  long long *boff = nullptr;
+  long long *boff = nullptr, *sub = nullptr;
   // kept by the plan
   long long *soff = nullptr;
   unsigned long long *eoff = nullptr;
@@ -502,6 +525,7 @@ int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, 
   if (e == hipSuccess) e = get(&ecnt, N * sizeof(unsigned), true);
   if (e == hipSuccess) e = get(&bsum, nblk * sizeof(unsigned), true);
   if (e == hipSuccess) e = get(&boff, (nblk + 1) * sizeof(long long), true);
+  if (e == hipSuccess) e = get(&sub, (nsub + 1) * sizeof(long long), true);
   if (e == hipSuccess) e = get(&soff, (nbin + 1) * sizeof(long long), false);
   if (e == hipSuccess) e = get(&eoff, (N + 1) * sizeof(unsigned long long), false);
   if (e != hipSuccess) {
@@ -513,13 +537,15 @@ int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, 
     lmh::set_error("tile binning: %s", hipGetErrorString(he));
     return LM_EHIP;
   };
-  if ((e = hipMemsetAsync(cnt, 0, nbin * sizeof(unsigned), st)) != hipSuccess) return fail(e);
-  for (int i = 0; i < nsub; ++i) {
-    const long long m = off[i + 1] - off[i];
-    if (m == 0) continue;
-    hipLaunchKernelGGL(k_tile_count, dim3(blocks(m, 256)), dim3(256), 0, st, g, tg, maxp, rec + off[i], m,
-                       cnt + (long long)i * tg.ntiles, ecnt + off[i]);
-  }
+  // the host copy stays alive until the synchronisation below
+  const std::vector<long long> hsub(off.begin(), off.end());
+  if ((e = hipMemcpyAsync(sub, hsub.data(), (nsub + 1) * sizeof(long long), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemsetAsync(cnt, 0, nbin * sizeof(unsigned), st)) != hipSuccess)
+    return fail(e);
+  for (long long e0 = 0; e0 < N; e0 += kChunk)
+    hipLaunchKernelGGL(k_tile_count, dim3(blocks(std::min(kChunk, N - e0), 256)), dim3(256), 0, st, g, tg, maxp,
+                       rec, e0, N, sub, nsub, cnt, ecnt);
   hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, cnt, nbin, soff);
   hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nblk), dim3(kScanB), 0, st, ecnt, N, bsum);
   hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, bsum, nblk, boff);
@@ -554,12 +580,9 @@ int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, 
   if ((e = hipMemcpyAsync(ord, order.data(), tg.ntiles * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemsetAsync(cnt, 0, nbin * sizeof(unsigned), st)) != hipSuccess)
     return fail(e);
-  for (int i = 0; i < nsub; ++i) {
-    const long long m = off[i + 1] - off[i];
-    if (m == 0) continue;
-    hipLaunchKernelGGL(k_tile_place, dim3(blocks(m, 256)), dim3(256), 0, st, g, tg, maxp, rec + off[i], m,
-                       soff + (long long)i * tg.ntiles, cnt + (long long)i * tg.ntiles, eoff + off[i], seg);
-  }
+  for (long long e0 = 0; e0 < N; e0 += kChunk)
+    hipLaunchKernelGGL(k_tile_place, dim3(blocks(std::min(kChunk, N - e0), 256)), dim3(256), 0, st, g, tg, maxp,
+                       rec, e0, N, sub, nsub, soff, cnt, eoff, seg);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   // the host order vector dies with this call
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e);
