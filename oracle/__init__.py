@@ -90,9 +90,6 @@ def _load():
         lib.orc_fwd.argtypes = [gp, dp, sp, ctypes.c_int64, dp]
         lib.orc_back.argtypes = [gp, dp, sp, ctypes.c_int64, dp]
         lib.orc_sens.argtypes = [gp, dp]
-        lib.orc_sens_pairs.argtypes = [gp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, dp]
-        lib.orc_count_samples.argtypes = [gp, sp, ctypes.c_int64]
-        lib.orc_count_samples.restype = ctypes.c_int64
         lib.orc_tof_weight.argtypes = [gp, ctypes.c_int, ctypes.c_double]
         lib.orc_tof_weight.restype = ctypes.c_double
         _lib = lib
@@ -183,23 +180,6 @@ def sens(geom: Geometry) -> np.ndarray:
     out = np.zeros(geom.shape, dtype=np.float64)
     lib.orc_sens(ctypes.byref(geom._c), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
-
-
-def sens_pairs(geom: Geometry, pairs: np.ndarray) -> np.ndarray:
-    """P^T 1 over the given crystal-id pairs (int32 [M, 2]) and all TOF bins."""
-    lib = _load()
-    pr = np.ascontiguousarray(pairs, dtype=np.int32)
-    out = np.zeros(geom.shape, dtype=np.float64)
-    lib.orc_sens_pairs(ctypes.byref(geom._c), pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                       len(pr), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-    return out
-
-
-def count_samples(geom: Geometry, events) -> int:
-    """Number of Joseph samples (plane x event with non-zero TOF weight)."""
-    ev = _ev(events)
-    return int(_load().orc_count_samples(ctypes.byref(geom._c),
-                                         ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), len(ev)))
 
 
 def tof_weight(geom: Geometry, k: int, t: float) -> float:

@@ -82,11 +82,10 @@ enum { W_BIN = 0, W_ALL_BINS = 1 };
 
 /*
  * Trace one LOR.  If x != NULL the forward value is returned; if img != NULL,
- * v * (row of P) is added into img.  Returns the number of samples with a
- * non-zero TOF weight through *nsamp when nsamp != NULL.
+ * v * (row of P) is added into img.
  */
 static double trace(const orc_geom *g, int id1, int id2, int k, int wmode,
-                    const double *x, double v, double *img, int64_t *nsamp) {
+                    const double *x, double v, double *img) {
   const float *f1 = g->det + 3 * (int64_t)id1;
   const float *f2 = g->det + 3 * (int64_t)id2;
   double p1[3], d[3];
@@ -125,7 +124,6 @@ static double trace(const orc_geom *g, int id1, int id2, int k, int wmode,
       for (int kk = -kmax; kk <= kmax; ++kk) w += orc_tof_weight(g, kk, t);
     }
     if (w == 0.0) continue;
-    if (nsamp) ++*nsamp;
     const double u1 = (p1[b1] + lam * d[b1] - c01) / g->h[b1];
     const double u2 = (p1[b2] + lam * d[b2] - c02) / g->h[b2];
     const double i1f = floor(u1), i2f = floor(u2);
@@ -164,7 +162,7 @@ void orc_fwd(const orc_geom *g, const double *x, const int16_t *ev, int64_t n, d
   for (int64_t e = 0; e < n; ++e) {
     int id1, id2, k;
     ids(g, ev + 5 * e, &id1, &id2, &k);
-    out[e] = trace(g, id1, id2, k, W_BIN, x, 0.0, NULL, NULL);
+    out[e] = trace(g, id1, id2, k, W_BIN, x, 0.0, NULL);
   }
 }
 
@@ -173,19 +171,8 @@ void orc_back(const orc_geom *g, const double *v, const int16_t *ev, int64_t n, 
   for (int64_t e = 0; e < n; ++e) {
     int id1, id2, k;
     ids(g, ev + 5 * e, &id1, &id2, &k);
-    trace(g, id1, id2, k, W_BIN, NULL, v[e], img, NULL);
+    trace(g, id1, id2, k, W_BIN, NULL, v[e], img);
   }
-}
-
-/* Number of Joseph samples (plane x event with non-zero TOF weight). */
-int64_t orc_count_samples(const orc_geom *g, const int16_t *ev, int64_t n) {
-  int64_t cnt = 0;
-  for (int64_t e = 0; e < n; ++e) {
-    int id1, id2, k;
-    ids(g, ev + 5 * e, &id1, &id2, &k);
-    trace(g, id1, id2, k, W_BIN, NULL, 0.0, NULL, &cnt);
-  }
-  return cnt;
 }
 
 /* g += P^T 1 summed over every unordered crystal pair id1 < id2 and every
@@ -194,11 +181,5 @@ void orc_sens(const orc_geom *g, double *img) {
   const int nd = g->n_cry * g->n_ring;
   for (int i1 = 0; i1 < nd; ++i1)
     for (int i2 = i1 + 1; i2 < nd; ++i2)
-      trace(g, i1, i2, 0, W_ALL_BINS, NULL, 1.0, img, NULL);
-}
-
-/* Sensitivity restricted to an explicit list of crystal pairs. */
-void orc_sens_pairs(const orc_geom *g, const int32_t *pairs, int64_t n, double *img) {
-  for (int64_t e = 0; e < n; ++e)
-    trace(g, pairs[2 * e], pairs[2 * e + 1], 0, W_ALL_BINS, NULL, 1.0, img, NULL);
+      trace(g, i1, i2, 0, W_ALL_BINS, NULL, 1.0, img);
 }

@@ -323,6 +323,39 @@ def test_cost_decreases(orc):
     assert costs[-1] <= min(costs[:3]) + 1e-9 * abs(c0)
 
 
+def test_cost_equals_sinogram_objective(orc):
+    """The listmode objective equals Eq. (1) written over every sinogram bin
+    (dense P, binned counts d, the contamination of every bin) less the
+    constant sum of s, with the TV term summed voxel by voxel: the data
+    term's sign, the <g, x> term, the isotropic norm and the place of beta
+    each change the value."""
+    p, ev, s, _ = tiny_problem(n_events=500, seed=23)
+    G = orc.Geometry.from_problem(p)
+    bins, _, d = _sino_setup(orc, p, ev)
+    P = orc.dense_matrix(G, bins)
+    rng = np.random.default_rng(24)
+    shape = p.image.shape_zyx
+    x = rng.uniform(0.2, 2.0, size=shape)
+    g = P.sum(axis=0).reshape(shape)
+    sb = np.full(len(bins), 0.05)
+    q = P @ x.reshape(-1) + sb
+    data = float((q - d * np.log(q)).sum() - sb.sum())
+    tv = 0.0
+    nz, ny, nx = shape
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                dx = x[k, j, i + 1] - x[k, j, i] if i + 1 < nx else 0.0
+                dy = x[k, j + 1, i] - x[k, j, i] if j + 1 < ny else 0.0
+                dz = x[k + 1, j, i] - x[k, j, i] if k + 1 < nz else 0.0
+                tv += np.sqrt(dx * dx + dy * dy + dz * dz)
+    beta = 0.07
+    want = data + beta * tv
+    got = orc.cost(G, x, ev, s, g, beta)
+    assert abs(got - want) <= 1e-11 * abs(want)
+    assert abs(orc.cost(G, x, ev, s, g, 0.0) - data) <= 1e-11 * abs(data)
+
+
 # ------------------------------------- conditioning of the TV dual w
 
 
