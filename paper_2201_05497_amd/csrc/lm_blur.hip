@@ -3,7 +3,7 @@
 // convolution, zero outside the image, so that B is symmetric and the back
 // projection applies the same B after G^T.  One pass per blurred axis over
 // the plan's bricked images; each voxel reads 2 r + 1 neighbours along the
-// axis (L2 hits) and writes one value: bound by HBM bandwidth.
+// axis (L2 hits, all loads in flight at once) and writes one value.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,6 +29,28 @@ __device__ __forceinline__ void vpos32(const lmk::Layout &L, unsigned p, int &i,
   k = (int)((bk << L.sz) | (loc >> (L.sx + L.sy)));
 }
 
+// The blur along one axis at the voxel of layout position p with
+// coordinate c0 along that axis (n voxels): the sum over t = -R..R, in that
+// order, of w[t + R] x(c0 + t), taps outside the image skipped.  The 2R + 1
+// loads (at clamped, always valid positions) are all issued before the
+// first product, so a wavefront waits for memory once per voxel, not once
+// per tap.
+template <int R>
+__device__ __forceinline__ float blur_at(const float *__restrict__ in, const lmk::AxisTerm &ta, unsigned p, int c0,
+                                         int n, const lmk::BlurAxis &taps) {
+  const int base = (int)p - lmk::axis_index(ta, c0);
+  float v[2 * R + 1];
+#pragma unroll
+  for (int t = -R; t <= R; ++t) v[t + R] = in[base + lmk::axis_index(ta, min(max(c0 + t, 0), n - 1))];
+  float acc = 0.0f;
+#pragma unroll
+  for (int t = -R; t <= R; ++t)
+    if (c0 + t >= 0 && c0 + t < n) acc = fmaf(taps.w[t + R], v[t + R], acc);
+  return acc;
+}
+
+// out = blur of `in` along `axis` with radius R (= taps.r).
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_blur_axis(const float *__restrict__ in, float *__restrict__ out,
                                                       lmk::Layout L, int nx, int ny, int nz, long long ne, int axis,
                                                       lmk::BlurAxis taps) {
@@ -38,21 +60,14 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis(const float *__restrict__ 
   vpos32(L, p, c[0], c[1], c[2]);
   if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding
   const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
-  const int c0 = c[axis];
-  float acc = 0.0f;
-  for (int t = -taps.r; t <= taps.r; ++t) {
-    const int q = c0 + t;
-    if (q < 0 || q >= n) continue;
-    c[axis] = q;
-    acc = fmaf(taps.w[t + taps.r], in[lmk::vidx(L, c[0], c[1], c[2])], acc);
-  }
-  out[p] = acc;
+  out[p] = blur_at<R>(in, lmk::axis_term(L, axis), p, c[axis], n, taps);
 }
 
 // The last blur pass of a data update's back projection fused with the z
 // step: d = (blur along `axis` of src)_p, z += d, zbar = z + d inv_p,
 // fuse ? x = max(0, x - T zbar) : store zbar, and dz = 0 for the next
 // update's atomics (dz is not read by this pass: src is a temporary).
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_blur_axis_dual(const float *__restrict__ src, float *__restrict__ dz,
                                                            float *__restrict__ z, float *__restrict__ x,
                                                            const float *__restrict__ T, float *__restrict__ zbar,
@@ -64,14 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis_dual(const float *__restri
   vpos32(L, p, c[0], c[1], c[2]);
   if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding (stays zero)
   const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
-  const int c0 = c[axis];
-  float d = 0.0f;
-  for (int t = -taps.r; t <= taps.r; ++t) {
-    const int q = c0 + t;
-    if (q < 0 || q >= n) continue;
-    c[axis] = q;
-    d = fmaf(taps.w[t + taps.r], src[lmk::vidx(L, c[0], c[1], c[2])], d);
-  }
+  const float d = blur_at<R>(src, lmk::axis_term(L, axis), p, c[axis], n, taps);
   const float zn = z[p] + d;
   const float zb = fmaf(d, inv_p, zn);
   z[p] = zn;
@@ -80,6 +88,48 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis_dual(const float *__restri
   else
     zbar[p] = zb;
   dz[p] = 0.0f;
+}
+
+// The kernels of radius taps.r (0..kMaxBlurRadius).
+#define LM_BLUR_RADII(M) \
+  M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
+static_assert(lmk::kMaxBlurRadius == 16, "one kernel per radius up to kMaxBlurRadius");
+
+int launch_axis(const float *in, float *out, const lmk::Layout &L, const int n[3], long long ne, int axis,
+                const lmk::BlurAxis &taps, hipStream_t st) {
+  switch (taps.r) {
+#define LM_CASE(R_)                                                                                              \
+  case R_:                                                                                                       \
+    hipLaunchKernelGGL((k_blur_axis<R_>), dim3(grid_for(ne)), dim3(kBlock), 0, st, in, out, L, n[0], n[1], n[2], \
+                       ne, axis, taps);                                                                          \
+    break;
+    LM_BLUR_RADII(LM_CASE)
+#undef LM_CASE
+    default:
+      lmh::set_error("blur radius %d outside 0..%d", taps.r, lmk::kMaxBlurRadius);
+      return LM_EINVAL;
+  }
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
+}
+
+int launch_axis_dual(const float *src, float *dz, float *z, float *x, const float *T, float *zbar, float inv_p,
+                     bool fuse, const lmk::Layout &L, const int n[3], long long ne, int axis,
+                     const lmk::BlurAxis &taps, hipStream_t st) {
+  switch (taps.r) {
+#define LM_CASE(R_)                                                                                              \
+  case R_:                                                                                                       \
+    hipLaunchKernelGGL((k_blur_axis_dual<R_>), dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dz, z, x, T, zbar,  \
+                       inv_p, fuse ? 1 : 0, L, n[0], n[1], n[2], ne, axis, taps);                                \
+    break;
+    LM_BLUR_RADII(LM_CASE)
+#undef LM_CASE
+    default:
+      lmh::set_error("blur radius %d outside 0..%d", taps.r, lmk::kMaxBlurRadius);
+      return LM_EINVAL;
+  }
+  LM_TRY_HIP(hipGetLastError());
+  return LM_OK;
 }
 
 }  // namespace
@@ -120,9 +170,7 @@ int launch_blur(const int n[3], const Layout &L, long long ne, const Blur &b, co
   const float *src = in;
   for (int k = 0; k < na; ++k) {
     float *dst = k + 1 == na ? out : (k % 2 == 0 ? t1 : t2);
-    hipLaunchKernelGGL(k_blur_axis, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2], ne,
-                       axes[k], b.ax[axes[k]]);
-    LM_TRY_HIP(hipGetLastError());
+    if (int rc = launch_axis(src, dst, L, n, ne, axes[k], b.ax[axes[k]], st)) return rc;
     src = dst;
   }
   return LM_OK;
@@ -141,9 +189,7 @@ int launch_blur_dual_image(const int n[3], const Layout &L, long long ne, const 
   const int plain = na == 1 ? 1 : na - 1;
   for (int k = 0; k < plain; ++k) {
     float *dst = k % 2 == 0 ? t1 : t2;
-    hipLaunchKernelGGL(k_blur_axis, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dst, L, n[0], n[1], n[2], ne,
-                       axes[k], b.ax[axes[k]]);
-    LM_TRY_HIP(hipGetLastError());
+    if (int rc = launch_axis(src, dst, L, n, ne, axes[k], b.ax[axes[k]], st)) return rc;
     src = dst;
   }
   BlurAxis last{};
@@ -155,10 +201,7 @@ int launch_blur_dual_image(const int n[3], const Layout &L, long long ne, const 
     axis = axes[na - 1];
     last = b.ax[axis];
   }
-  hipLaunchKernelGGL(k_blur_axis_dual, dim3(grid_for(ne)), dim3(kBlock), 0, st, src, dz, z, x, T, zbar, inv_p,
-                     fuse ? 1 : 0, L, n[0], n[1], n[2], ne, axis, last);
-  LM_TRY_HIP(hipGetLastError());
-  return LM_OK;
+  return launch_axis_dual(src, dz, z, x, T, zbar, inv_p, fuse, L, n, ne, axis, last, st);
 }
 
 }  // namespace lmk
