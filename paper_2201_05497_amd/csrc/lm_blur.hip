@@ -10,24 +10,13 @@
 
 #include "lm_blur.hpp"
 #include "lm_host.hpp"
+#include "lm_layout32.hpp"
 
 namespace {
 
 constexpr int kBlock = 256;
 
 inline unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-
-// Position p of layout L -> voxel (i, j, k) in 32-bit arithmetic (images
-// hold fewer than 2^31 elements; 64-bit division would dominate the pass).
-__device__ __forceinline__ void vpos32(const lmk::Layout &L, unsigned p, int &i, int &j, int &k) {
-  const int sh = L.sx + L.sy + L.sz;
-  const unsigned b = p >> sh, loc = p & ((1u << sh) - 1u);
-  const unsigned row = b / (unsigned)L.nbx, bi = b - row * (unsigned)L.nbx;
-  const unsigned bk = row / (unsigned)L.nby, bj = row - bk * (unsigned)L.nby;
-  i = (int)((bi << L.sx) | (loc & ((1u << L.sx) - 1u)));
-  j = (int)((bj << L.sy) | ((loc >> L.sx) & ((1u << L.sy) - 1u)));
-  k = (int)((bk << L.sz) | (loc >> (L.sx + L.sy)));
-}
 
 // The blur along one axis at the voxel of layout position p with
 // coordinate c0 along that axis (n voxels): the sum over t = -R..R, in that
@@ -57,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis(const float *__restrict__ 
   const unsigned p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int c[3];
-  vpos32(L, p, c[0], c[1], c[2]);
+  lmk::vpos32(L, p, c[0], c[1], c[2]);
   if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding
   const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
   out[p] = blur_at<R>(in, lmk::axis_term(L, axis), p, c[axis], n, taps);
@@ -76,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_blur_axis_dual(const float *__restri
   const unsigned p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int c[3];
-  vpos32(L, p, c[0], c[1], c[2]);
+  lmk::vpos32(L, p, c[0], c[1], c[2]);
   if (c[0] >= nx || c[1] >= ny || c[2] >= nz) return;  // padding (stays zero)
   const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
   const float d = blur_at<R>(src, lmk::axis_term(L, axis), p, c[axis], n, taps);

@@ -16,6 +16,7 @@
 
 #include "lm_dtv.hpp"
 #include "lm_host.hpp"
+#include "lm_layout32.hpp"
 
 namespace {
 
@@ -47,10 +48,10 @@ __global__ __launch_bounds__(kBlock) void k_dtv_dual(const float *__restrict__ x
                                                      float *__restrict__ w_out, const float *__restrict__ xi,
                                                      float *__restrict__ pd, lmk::Layout L, int nx, int ny, int nz,
                                                      long long ne, int ncomp, float Sp, float beta) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const unsigned p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int i, j, k;
-  lmk::vpos(L, p, i, j, k);
+  lmk::vpos32(L, p, i, j, k);
   if (i >= nx || j >= ny || k >= nz) return;  // padding
   const float c = x[p];
   float g[3], e[3], wv[3];
@@ -91,10 +92,10 @@ __global__ __launch_bounds__(kBlock) void k_dtv_adjoint_image(const float *__res
                                                               float *__restrict__ zbar, float inv_p, int fuse,
                                                               lmk::Layout L, int nx, int ny, int nz, long long ne,
                                                               int ncomp) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const unsigned p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= ne) return;
   int i, j, k;
-  lmk::vpos(L, p, i, j, k);
+  lmk::vpos32(L, p, i, j, k);
   if (i >= nx || j >= ny || k >= nz) return;
   float s = 0.0f;
   if (i > 0) s += pd[lmk::vidx(L, i - 1, j, k)];
