@@ -90,11 +90,10 @@ BYTES_PER_EVENT_PROJ = 10 + 4
 # reads ubar and q (4 + 12) and writes q (12); the primal pass reads u, z,
 # w and q (4 + 4 + 4 + 12) and writes u and ubar (8).
 BYTES_PER_VOXEL_PD = 28 + 32
-# A DTV prior update, per voxel: the dual pass reads x, w and xi (4 + 12 +
-# 12) and writes w and D (w_new - w) (12 + 12); the adjoint pass, fused with
-# z / zbar and the primal step, reads the latter, z, T and x (12 + 12) and
-# writes z and x (8).
-BYTES_PER_VOXEL_DTV = 52 + 32
+# A DTV prior update in 3D, one pass per voxel (the TV pass's bytes plus
+# xi): reads x, w, xi, z and T (4 + 12 + 12 + 4 + 4) and writes w, z and x
+# (12 + 4 + 4).
+BYTES_PER_VOXEL_DTV = 56
 WARM_SUBSETS = 28               # the paper's warm start: 1 EM-TV iteration, 28 subsets,
 WARM_DENOISE = 20               # 20 accelerated PDHG steps per denoising
 

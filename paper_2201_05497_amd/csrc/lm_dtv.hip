@@ -5,13 +5,14 @@
 // vector its component along xi; it is symmetric with |D_j| <= 1, so the
 // step sizes computed with ||grad|| stay valid.
 //
-// The prior update is two passes over the plan's bricked images: the dual
-// step (forward differences of x at the voxel, D, the projection onto the
-// beta-ball) storing D (w_out - w), then its adjoint stencil fused with the
-// z / zbar step and the next primal step.  The first pass reads x, w, xi and
-// writes w_out and D (w_out - w) (ncomp components each); the second reads
-// the latter back with z, T and x and writes z and x (or zbar): bound by
-// HBM bandwidth.
+// In 3D the prior update is the TV pass marching along z with xi read next
+// to w (k_tv_march in lm_image.hip).  On one slice it is two passes over
+// the plan's bricked images: the dual step (forward differences of x at the
+// voxel, D, the projection onto the beta-ball) storing D (w_out - w), then
+// its adjoint stencil fused with the z / zbar step and the next primal
+// step.  The first pass reads x, w, xi and writes w_out and D (w_out - w)
+// (ncomp components each); the second reads the latter back with z, T and
+// x and writes z and x (or zbar): bound by HBM bandwidth.
 #include <hip/hip_runtime.h>
 
 #include "lm_dtv.hpp"

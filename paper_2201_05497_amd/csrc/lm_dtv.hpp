@@ -12,7 +12,9 @@ namespace lmk {
 int launch_dtv_field(const int n[3], const Layout &L, int ncomp, long long ne, const float *v, float eta, float *xi,
                      hipStream_t st);
 
-// Prior update of LM-SPDHG with K = D grad, D = I - xi xi^T:
+// Prior update of LM-SPDHG with K = D grad, D = I - xi xi^T, in two passes
+// (the plan uses it for one-slice images; 3D images take launch_tv_fused
+// with xi):
 // w_out = proj_beta(w + Sp D grad x), dz = grad^T D (w_out - w) (pd holds
 // D (w_out - w), ncomp components), z += dz, zbar = z + dz inv_p, and
 // fuse ? x = max(0, x - T zbar) in place : store zbar.  All in layout L.

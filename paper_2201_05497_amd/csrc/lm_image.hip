@@ -183,7 +183,10 @@ __device__ __forceinline__ int brick_ij(int nbx, int i, int j) {
 }
 
 // The whole prior update for a 3D image in the 4x4x4 brick layout, marching
-// along z two planes per step.  A block owns a 16 x 16 column and a run of
+// along z two planes per step: TV, or with DTV = true the directional TV of
+// Section 3 (K = D grad, D = I - xi xi^T per voxel: the dual step takes D g
+// and K^T takes D (w+ - w); xi is read next to w, 56 instead of 44 bytes
+// per voxel).  A block owns a 16 x 16 column and a run of
 // CZ planes (CZ even, so a step covers planes k and k+1 of one brick layer
 // and writes whole 128-byte lines of every brick).  Thread t owns voxel
 // (t & 3) + 4 (t >> 4 & 3), ((t >> 2) & 3) + 4 (t >> 6) of the column in
@@ -199,9 +202,10 @@ __device__ __forceinline__ int brick_ij(int nbx, int i, int j) {
 // step ahead); w, z and T of the next two planes are loaded one step ahead.
 // Threads 0..31 compute the lower-face dual steps of plane k, threads
 // 32..63 those of plane k+1; threads 0..135 load the x ring of two planes.
-template <int CZ>
+template <int CZ, bool DTV>
 __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x, const float *__restrict__ w,
-                                                      float *__restrict__ w_out, float *__restrict__ z,
+                                                      const float *__restrict__ xi, float *__restrict__ w_out,
+                                                      float *__restrict__ z,
                                                       float *__restrict__ x_out, const float *__restrict__ T,
                                                       float *__restrict__ zbar, int nbx, int nby, int nx, int ny,
                                                       int nz, long long ne, float Sp, float beta, float inv_p,
@@ -261,13 +265,48 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
   // plane k + rpl (0 where outside the image)
   auto load_own = [&](int k) { return (own && k < nz) ? x[own_ij + koff(k)] : 0.0f; };
   auto load_ring = [&](int k) { return (r_ok && k + rpl < nz) ? x[r_ij + koff(k + rpl)] : 0.0f; };
-  auto prox = [&](float gx, float gy, float gz, float w0, float w1, float w2, float &q0, float &q1, float &q2) {
-    const float v0 = fmaf(Sp, gx, w0), v1 = fmaf(Sp, gy, w1), v2 = fmaf(Sp, gz, w2);
+  // dual step at a voxel with forward differences g and dual w: q = the
+  // increment K^T needs, wn = the new dual.  TV: q = wn - w.  DTV (K = D
+  // grad, D = I - e e^T with e the voxel's xi): the step takes D g, and q =
+  // D (wn - w).
+  auto prox = [&](float gx, float gy, float gz, const float (&wv)[3], const float (&e)[3], float (&q)[3],
+                  float (&wn)[3]) {
+    if constexpr (DTV) {
+      const float eg = fmaf(e[2], gz, fmaf(e[1], gy, e[0] * gx));
+      gx = fmaf(-e[0], eg, gx);
+      gy = fmaf(-e[1], eg, gy);
+      gz = fmaf(-e[2], eg, gz);
+    }
+    const float v0 = fmaf(Sp, gx, wv[0]), v1 = fmaf(Sp, gy, wv[1]), v2 = fmaf(Sp, gz, wv[2]);
     const float nrm = sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
     const float sc = 1.0f / fmaxf(1.0f, nrm / beta);
-    q0 = v0 * sc - w0;
-    q1 = v1 * sc - w1;
-    q2 = v2 * sc - w2;
+    if constexpr (DTV) {
+      wn[0] = v0 * sc;
+      wn[1] = v1 * sc;
+      wn[2] = v2 * sc;
+      const float d0 = wn[0] - wv[0], d1 = wn[1] - wv[1], d2 = wn[2] - wv[2];
+      const float ed = fmaf(e[2], d2, fmaf(e[1], d1, e[0] * d0));
+      q[0] = fmaf(-e[0], ed, d0);
+      q[1] = fmaf(-e[1], ed, d1);
+      q[2] = fmaf(-e[2], ed, d2);
+    } else {
+      q[0] = v0 * sc - wv[0];
+      q[1] = v1 * sc - wv[1];
+      q[2] = v2 * sc - wv[2];
+      wn[0] = wv[0] + q[0];
+      wn[1] = wv[1] + q[1];
+      wn[2] = wv[2] + q[2];
+    }
+  };
+  // xi of layout position p (DTV), else zeros
+  auto load_e = [&](int p, float (&e)[3]) {
+    if constexpr (DTV) {
+      e[0] = xi[p];
+      e[1] = xi[ne + p];
+      e[2] = xi[2 * ne + p];
+    } else {
+      e[0] = e[1] = e[2] = 0.0f;
+    }
   };
   // dual step of the plane below the run, own voxels only (its z-component
   // feeds the first plane's z-difference)
@@ -278,20 +317,22 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
     xb[0][own_b] = load_own(kb);
     if (rb >= 0 && rpl == 0) xb[0][rb] = load_ring(kb);
     const float xup = load_own(kz0);
-    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+    float wb[3] = {0.0f, 0.0f, 0.0f}, eb[3] = {0.0f, 0.0f, 0.0f};
     if (own) {
       const int p = own_ij + koff(kb);
-      w0 = w[p];
-      w1 = w[ne + p];
-      w2 = w[2 * ne + p];
+      wb[0] = w[p];
+      wb[1] = w[ne + p];
+      wb[2] = w[2 * ne + p];
+      load_e(p, eb);
     }
     __syncthreads();
     const float xv = xb[0][own_b];
     const float gx = (i < nx - 1) ? xb[0][own_b + 1] - xv : 0.0f;
     const float gy = (j < ny - 1) ? xb[0][own_b + B] - xv : 0.0f;
     const float gz = xup - xv;  // kb < nz - 1
-    float q0, q1;
-    prox(gx, gy, gz, w0, w1, w2, q0, q1, q2prev);
+    float qb[3], wnb[3];
+    prox(gx, gy, gz, wb, eb, qb, wnb);
+    q2prev = qb[2];
     __syncthreads();
   }
   // planes kz0, kz0+1, kz0+2 into LDS; kz0+3, kz0+4 into registers
@@ -310,11 +351,14 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
     }
   }
   float pxo0 = load_own(kz0 + 3), pxo1 = load_own(kz0 + 4), pxr = load_ring(kz0 + 3);
-  // w, z, T of the own voxel for planes k, k+1; w of the face voxel
-  float wo[2][3], zo[2], to[2], wh[3];
-  auto load_w = [&](int k, float (&wv)[2][3], float (&zv)[2], float (&tv)[2], float (&whv)[3]) {
+  // w, z, T (and xi) of the own voxel for planes k, k+1; w (and xi) of the
+  // face voxel
+  float wo[2][3], zo[2], to[2], wh[3], eo[2][3], eh[3];
+  auto load_w = [&](int k, float (&wv)[2][3], float (&zv)[2], float (&tv)[2], float (&whv)[3], float (&ev)[2][3],
+                    float (&ehv)[3]) {
     for (int s = 0; s < 2; ++s) {
       wv[s][0] = wv[s][1] = wv[s][2] = zv[s] = tv[s] = 0.0f;
+      ev[s][0] = ev[s][1] = ev[s][2] = 0.0f;
       if (own && k + s < kz1) {
         const int p = own_ij + koff(k + s);
         wv[s][0] = w[p];
@@ -322,23 +366,26 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
         wv[s][2] = w[2 * ne + p];
         zv[s] = z[p];
         if (fuse) tv[s] = T[p];
+        load_e(p, ev[s]);
       }
     }
     whv[0] = whv[1] = whv[2] = 0.0f;
+    ehv[0] = ehv[1] = ehv[2] = 0.0f;
     if (h_ok && k + hpl < kz1) {
       const int p = h_ij + koff(k + hpl);
       whv[0] = w[p];
       whv[1] = w[ne + p];
       whv[2] = w[2 * ne + p];
+      load_e(p, ehv);
     }
   };
-  load_w(kz0, wo, zo, to, wh);
+  load_w(kz0, wo, zo, to, wh, eo, eh);
   __syncthreads();
   for (int k = kz0; k < kz1; k += 2) {
     // loads for the next step: x of planes k+5, k+6; w, z, T of k+2, k+3
     const float nxo0 = load_own(k + 5), nxo1 = load_own(k + 6), nxr = load_ring(k + 5);
-    float nwo[2][3], nzo[2], nto[2], nwh[3];
-    load_w(k + 2, nwo, nzo, nto, nwh);
+    float nwo[2][3], nzo[2], nto[2], nwh[3], neo[2][3], neh[3];
+    load_w(k + 2, nwo, nzo, nto, nwh, neo, neh);
     const float *xa = xb[bk0], *xc = xb[bk1], *xd = xb[bk2];
     // own dual steps of planes k (s = 0) and k+1 (s = 1)
     float q[2][3], xv[2];
@@ -349,19 +396,20 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
       const float gx = (i < nx - 1) ? xs[own_b + 1] - xv[s] : 0.0f;
       const float gy = (j < ny - 1) ? xs[own_b + B] - xv[s] : 0.0f;
       const float gz = (kk < nz - 1) ? xu[own_b] - xv[s] : 0.0f;
-      prox(gx, gy, gz, wo[s][0], wo[s][1], wo[s][2], q[s][0], q[s][1], q[s][2]);
+      float wn[3];
+      prox(gx, gy, gz, wo[s], eo[s], q[s], wn);
       q0s[s][own_q] = q[s][0];
       q1s[s][own_q] = q[s][1];
       if (own && kk < kz1) {
         const int p = own_ij + koff(kk);
-        w_out[p] = wo[s][0] + q[s][0];
-        w_out[ne + p] = wo[s][1] + q[s][1];
-        w_out[2 * ne + p] = wo[s][2] + q[s][2];
+        w_out[p] = wn[0];
+        w_out[ne + p] = wn[1];
+        w_out[2 * ne + p] = wn[2];
       }
     }
     // lower-face dual steps (the component the own voxels need)
     if (t < 64) {
-      float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+      float hq3[3] = {0.0f, 0.0f, 0.0f};
       const int kk = k + hpl;
       if (h_ok && kk < kz1) {
         const float *xs = hpl ? xc : xa, *xu = hpl ? xd : xc;
@@ -369,12 +417,13 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
         const float gx = (hgi < nx - 1) ? xs[hb + 1] - hv : 0.0f;
         const float gy = (hgj < ny - 1) ? xs[hb + B] - hv : 0.0f;
         const float gz = (kk < nz - 1) ? xu[hb] - hv : 0.0f;
-        prox(gx, gy, gz, wh[0], wh[1], wh[2], h0, h1, h2);
+        float hwn[3];
+        prox(gx, gy, gz, wh, eh, hq3, hwn);
       }
       if ((t & 31) < 16)
-        q0s[hpl][hq] = h0;
+        q0s[hpl][hq] = hq3[0];
       else
-        q1s[hpl][hq] = h1;
+        q1s[hpl][hq] = hq3[1];
     }
     __syncthreads();
     // planes k+3, k+4 (loaded one step ago) replace k and k+1 in LDS
@@ -409,9 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_tv_march(const float *__restrict__ x
     for (int s = 0; s < 2; ++s) {
       zo[s] = nzo[s];
       to[s] = nto[s];
-      for (int c = 0; c < 3; ++c) wo[s][c] = nwo[s][c];
+      for (int c = 0; c < 3; ++c) {
+        wo[s][c] = nwo[s][c];
+        eo[s][c] = neo[s][c];
+      }
     }
-    for (int c = 0; c < 3; ++c) wh[c] = nwh[c];
+    for (int c = 0; c < 3; ++c) {
+      wh[c] = nwh[c];
+      eh[c] = neh[c];
+    }
     // the buffer of plane k+2 becomes plane k of the next step
     const int b0 = bk0, b1 = bk1;
     bk0 = bk2;
@@ -501,15 +556,24 @@ int launch_dual_image(float *z, float *dz, float *x, const float *T, float *zbar
   return LM_OK;
 }
 
-int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *w_out,
-                    float *z, float *x_out, const float *T, float *zbar, float Sp, float beta, float inv_p, bool fuse,
-                    hipStream_t st) {
+bool prior_march_ok(const Layout &L, int ncomp) { return L.sx == 2 && L.sy == 2 && L.sz == 2 && ncomp == 3; }
+
+int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, const float *xi,
+                    float *w_out, float *z, float *x_out, const float *T, float *zbar, float Sp, float beta,
+                    float inv_p, bool fuse, hipStream_t st) {
   const long long ne = layout_size(L);
-  if (L.sx == 2 && L.sy == 2 && L.sz == 2 && ncomp == 3) {
+  if (prior_march_ok(L, ncomp)) {
     constexpr int CZ = 16;
     const int nblocks = ((n[0] + 15) / 16) * ((n[1] + 15) / 16) * ((n[2] + CZ - 1) / CZ);
-    hipLaunchKernelGGL((k_tv_march<CZ>), dim3(nblocks), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T, zbar, L.nbx,
-                       L.nby, n[0], n[1], n[2], ne, Sp, beta, inv_p, fuse ? 1 : 0, nblocks);
+    if (xi)
+      hipLaunchKernelGGL((k_tv_march<CZ, true>), dim3(nblocks), dim3(kBlock), 0, st, x, w, xi, w_out, z, x_out, T,
+                         zbar, L.nbx, L.nby, n[0], n[1], n[2], ne, Sp, beta, inv_p, fuse ? 1 : 0, nblocks);
+    else
+      hipLaunchKernelGGL((k_tv_march<CZ, false>), dim3(nblocks), dim3(kBlock), 0, st, x, w, xi, w_out, z, x_out, T,
+                         zbar, L.nbx, L.nby, n[0], n[1], n[2], ne, Sp, beta, inv_p, fuse ? 1 : 0, nblocks);
+  } else if (xi) {
+    lmh::set_error("prior update by column march: the image layout must be 4x4x4 bricks with 3 components");
+    return LM_EINVAL;
   } else if (L.sx == 2 && L.sy == 2 && L.sz == 0 && n[2] == 1) {
     const int ntiles = ((L.nbx + 3) / 4) * ((L.nby + 3) / 4);
     hipLaunchKernelGGL((k_tv_tiled<4, 4, 1, 4, 4>), dim3(ntiles), dim3(kBlock), 0, st, x, w, w_out, z, x_out, T,

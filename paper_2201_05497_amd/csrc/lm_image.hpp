@@ -18,9 +18,14 @@ int launch_dual_image(float *z, float *dz, float *x, const float *T, float *zbar
 // The whole prior update in one pass: w_out = proj_beta(w + Sp K x),
 // dz = K^T(w_out - w), z += dz, zbar = z + dz inv_p, fuse ? x_out = max(0,
 // x - T zbar) : store zbar.  x and w are only read (x_out, w_out separate).
-int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, float *w_out,
-                    float *z, float *x_out, const float *T, float *zbar, float Sp, float beta, float inv_p, bool fuse,
-                    hipStream_t st);
+// K = grad (TV), or with xi != NULL K = D grad with D = I - xi xi^T per
+// voxel (DTV; xi: 3 components in layout L), which needs prior_march_ok.
+int launch_tv_fused(const int n[3], const Layout &L, int ncomp, const float *x, const float *w, const float *xi,
+                    float *w_out, float *z, float *x_out, const float *T, float *zbar, float Sp, float beta,
+                    float inv_p, bool fuse, hipStream_t st);
+// Layouts whose prior update runs as one pass marching along z (4x4x4
+// bricks, 3 components).
+bool prior_march_ok(const Layout &L, int ncomp);
 
 // Conversions between the caller's row-major images (ncomp components of
 // n[0] n[1] n[2] elements) and layout L (ncomp components of layout_size(L)).

@@ -642,9 +642,9 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
             }))
           return rc;
       }
-    } else if (p->dtv) {
-      // K = D grad: the dual step, then the adjoint fused with z / zbar and
-      // the next primal step (in place)
+    } else if (p->dtv && !lmk::prior_march_ok(p->lay, p->ncomp)) {
+      // K = D grad on one slice: the dual step, then the adjoint fused with
+      // z / zbar and the next primal step (in place)
       if (int rc = timed(p, LM_K_TV, st, [&] {
             return lmk::launch_dtv_prior(p->G.n, p->lay, p->ncomp, E, xi, p->w, p->wn, p->xi_dtv, p->pd, p->z,
                                          p->T, p->zbar, (float)p->Sp, (float)p->beta, inv_p_prior, fuse, st);
@@ -652,9 +652,11 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
         return rc;
       std::swap(p->w, p->wn);
     } else {
+      // TV, or DTV (K = D grad) in 3D: one pass
       if (int rc = timed(p, LM_K_TV, st, [&] {
-            return lmk::launch_tv_fused(p->G.n, p->lay, p->ncomp, xi, p->w, p->wn, p->z, p->xalt, p->T, p->zbar,
-                                        (float)p->Sp, (float)p->beta, inv_p_prior, fuse, st);
+            return lmk::launch_tv_fused(p->G.n, p->lay, p->ncomp, xi, p->w, p->dtv ? p->xi_dtv : nullptr, p->wn,
+                                        p->z, p->xalt, p->T, p->zbar, (float)p->Sp, (float)p->beta, inv_p_prior,
+                                        fuse, st);
           }))
         return rc;
       std::swap(p->w, p->wn);
