@@ -116,9 +116,9 @@ KERNEL_SOURCES = {
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
     # the data update by image tile: phase 1 (k_tile_fwd) + phase 2 (k_tile_back)
-    "data_update": {"fetch_bytes": 222700000, "write_bytes": 70100000, "sources": "e913f82319daca61",
+    "data_update": {"fetch_bytes": 222100000, "write_bytes": 70100000, "sources": "ad2010f8c9e6f27d",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
-    "tv": {"fetch_bytes": 106200000, "write_bytes": 76900000, "sources": "bbd499960c963172",
+    "tv": {"fetch_bytes": 106400000, "write_bytes": 77000000, "sources": "5157d7dc3cd01a2c",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     "dual_image": {"fetch_bytes": 61408650, "write_bytes": 46080000, "sources": "5bbf6922e857d5c6",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
@@ -134,7 +134,7 @@ PMC_TRAFFIC: dict = {
 # VALU wavefront instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU),
 # with the digest of the kernel's sources at the time.
 PMC_VALU: dict = {
-    "data_update": {"instr_per_launch": 46350000, "sources": "e913f82319daca61",
+    "data_update": {"instr_per_launch": 46350000, "sources": "ad2010f8c9e6f27d",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
 }
 
