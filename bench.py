@@ -106,8 +106,8 @@ KERNEL_SOURCES = {
     "dual_image": ["lm_image.hip"],
     "tv": ["lm_image.hip", "lm_device.hpp"],
     "primal": ["lm_image.hip"],
-    "fwd": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip"],
-    "back": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip"],
+    "fwd": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip", "lm_sort.hip", "lm_sort.hpp"],
+    "back": ["lm_project.hip", "lm_device.hpp", "lm_lines.hip", "lm_sort.hip", "lm_sort.hpp"],
 }
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and

@@ -92,8 +92,8 @@ const char *lm_last_error(void);
  * events ev[n][5] in the caller's order.  x: image; out: float[n].  Events
  * that are out of range get out[e] = 0.  On a cylindrical scanner (as for
  * lm_back, decided on the device) a list of at least 64 events per
- * transaxial crystal pair and fewer than 2^32 events is projected by
- * transaxial line after a counting sort on the device: 12 more bytes per
+ * transaxial crystal pair and fewer than 2^31 events is projected by
+ * transaxial line after a counting sort on the device: 16 more bytes per
  * event of stream-ordered temporary memory (without room for it the events
  * are projected in their own order).  The result is the same up to float32
  * rounding in either order.  The call never synchronises the stream. */
@@ -120,7 +120,7 @@ int lm_fwd_noalloc(const lm_geom *G, const float *x, const int16_t *ev, int64_t 
  * v = 0 contribute nothing.  On a cylindrical scanner (crystal c of ring r
  * at (x_c, y_c, z_r), z increasing with r) a list of at least 64 events per
  * transaxial crystal pair is back projected by transaxial line after a
- * counting sort on the device; the list then needs 16 more bytes per event
+ * counting sort on the device; the list then needs 32 more bytes per event
  * of stream-ordered temporary memory (without room for it the per-event
  * path runs).  Whether the scanner is cylindrical is decided by a kernel
  * that reads the crystal table: the call never synchronises the stream. */

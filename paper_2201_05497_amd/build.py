@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblmspdhg.so")
-SOURCES = ["lm_project.hip", "lm_image.hip", "lm_plan.hip", "lm_lines.hip", "lm_emtv.hip", "lm_dtv.hip", "lm_blur.hip", "lm_cost.hip", "lm_tiles.hip"]
+SOURCES = ["lm_project.hip", "lm_image.hip", "lm_plan.hip", "lm_lines.hip", "lm_emtv.hip", "lm_dtv.hip", "lm_blur.hip", "lm_cost.hip", "lm_tiles.hip", "lm_sort.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -22,6 +22,7 @@
 
 #include "lm_device.hpp"
 #include "lm_host.hpp"
+#include "lm_sort.hpp"
 
 using namespace lmk;
 
@@ -403,58 +404,18 @@ __device__ __forceinline__ int event_line(const GeomDev &g, const int16_t *e, fl
   return (int)(c1 * n - (long long)c1 * (c1 + 1) / 2 + (c2 - c1 - 1));
 }
 
-// Line of every event and its rank among its line's events (in no fixed
-// order: the rank comes from an atomic counter per line).
+// Line of every event (negative: not by line) and its record.
 __global__ __launch_bounds__(256) void k_line_keys(GeomDev g, const int *cyl, const int16_t *ev, const float *v,
-                                                   long long n, int *key, unsigned *rank, unsigned *cnt) {
+                                                   long long n, int *key, LineRec *rec) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n || !*cyl) return;
   unsigned rk;
   const int L = event_line(g, ev + 5 * e, v[e], rk);
   key[e] = L;
-  if (L >= 0) rank[e] = atomicAdd(cnt + L, 1u);
-}
-
-// Exclusive prefix sum of cnt[0 .. n) into off[0 .. n]; one block of 1024
-// threads, each summing a contiguous segment.
-__global__ __launch_bounds__(1024) void k_line_offsets(const int *cyl, const unsigned *cnt, long long n,
-                                                       unsigned *off) {
-  __shared__ unsigned part[1024];
-  if (cyl && !*cyl) return;
-  const int t = threadIdx.x;
-  const long long seg = (n + 1023) / 1024;
-  const long long a = min(n, t * seg), b = min(n, a + seg);
-  unsigned sum = 0;
-  for (long long i = a; i < b; ++i) sum += cnt[i];
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the segment sums
-    const unsigned add = t >= o ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
-  }
-  unsigned run = part[t] - sum;
-  for (long long i = a; i < b; ++i) {
-    off[i] = run;
-    run += cnt[i];
-  }
-  if (t == 1023) off[n] = part[1023];
-}
-
-__global__ __launch_bounds__(256) void k_line_place(GeomDev g, const int *cyl, const int16_t *ev, const float *v,
-                                                    long long n, const int *key, const unsigned *rank,
-                                                    const unsigned *off, LineRec *rec) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n || !*cyl) return;
-  const int L = key[e];
-  if (L < 0) return;
-  unsigned rk;
-  event_line(g, ev + 5 * e, v[e], rk);
   LineRec r;
   r.rk = rk;
   r.v = v[e];
-  rec[off[L] + rank[e]] = r;
+  rec[e] = r;
 }
 
 // Back projection of the events of every line (records rec[off[L] ..
@@ -563,12 +524,11 @@ __global__ __launch_bounds__(256) void k_back_zdom(GeomDev g, const int *cyl, co
   }
 }
 
-// The order of lm_fwd for a long list: bucket of every event (its
+// The order of lm_fwd for a long list: the bucket of every event (its
 // transaxial crystal pair c1 != c2 as line index; events of one crystal or
-// out of range in bucket nlines) and its rank there, then the events'
-// indices placed by bucket.
+// out of range in bucket nlines), grouped by group_by_key.
 __global__ __launch_bounds__(256) void k_fwd_keys(GeomDev g, const int16_t *ev, long long n, long long nlines,
-                                                  unsigned *key, unsigned *rank, unsigned *cnt) {
+                                                  unsigned *key) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   const int c1 = ev[5 * e], c2 = ev[5 * e + 2];
@@ -578,14 +538,6 @@ __global__ __launch_bounds__(256) void k_fwd_keys(GeomDev g, const int16_t *ev, 
     L = lo * nc - lo * (lo + 1) / 2 + (hi - lo - 1);
   }
   key[e] = (unsigned)L;
-  rank[e] = atomicAdd(cnt + L, 1u);
-}
-
-__global__ __launch_bounds__(256) void k_fwd_place(const unsigned *key, const unsigned *rank, const unsigned *off,
-                                                   long long n, unsigned *order) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  order[off[key[e]] + rank[e]] = (unsigned)e;
 }
 
 // ---------------------------------------------------------------------------
@@ -1003,17 +955,14 @@ int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsign
   *order = nullptr;
   if (offsets) *offsets = nullptr;
   const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
-  if (g.n_cry < 2 || n < 64 * nlines || n >= (1LL << 32) || nlines >= (1LL << 31)) return LM_OK;
-  unsigned *key = nullptr, *rank = nullptr, *cnt = nullptr, *off = nullptr, *ord = nullptr;
+  if (g.n_cry < 2 || n < 64 * nlines || n >= (1LL << 31) || nlines + 1 > (long long)kGroupMaxBuckets) return LM_OK;
+  unsigned *key = nullptr, *off = nullptr, *ord = nullptr;
   auto release = [&](bool keep) {  // release errors are not reported
-    for (unsigned *q : {key, rank, cnt})
-      if (q) (void)hipFreeAsync(q, st);
+    if (key) (void)hipFreeAsync(key, st);
     if (ord && !keep) (void)hipFreeAsync(ord, st);
     if (off && !(keep && offsets)) (void)hipFreeAsync(off, st);
   };
   hipError_t e = hipMallocAsync((void **)&key, n * sizeof(unsigned), st);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&rank, n * sizeof(unsigned), st);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, (nlines + 1) * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&off, (nlines + 2) * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&ord, n * sizeof(unsigned), st);
   if (e == hipErrorOutOfMemory) {
@@ -1021,16 +970,22 @@ int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsign
     (void)hipGetLastError();
     return LM_OK;  // the list is projected in its own order
   }
-  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, (nlines + 1) * sizeof(unsigned), st);
-  const unsigned grid = (unsigned)((n + 255) / 256);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_fwd_keys, dim3(grid), dim3(256), 0, st, g, ev, n, nlines, key, rank, cnt);
-    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, nullptr, cnt, nlines + 1, off);
-    hipLaunchKernelGGL(k_fwd_place, dim3(grid), dim3(256), 0, st, key, rank, off, n, ord);
+    hipLaunchKernelGGL(k_fwd_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, ev, n, nlines, key);
     e = hipGetLastError();
   }
-  release(e == hipSuccess);
-  LM_TRY_HIP(e);
+  if (e != hipSuccess) {
+    release(false);
+    LM_TRY_HIP(e);
+  }
+  const int rc = group_by_key(key, (const unsigned *)nullptr, n, (unsigned)(nlines + 1), nullptr, ord, off, st);
+  if (rc == LM_ENOMEM) {
+    release(false);
+    lmh::clear_error();
+    return LM_OK;  // the list is projected in its own order
+  }
+  release(rc == LM_OK);
+  if (rc != LM_OK) return rc;
   *order = ord;
   if (offsets) *offsets = off;
   return LM_OK;
@@ -1101,41 +1056,45 @@ int launch_back_lines(const GeomDev &g, const int *cyl, const float *v, const in
   queued = false;
   const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
   if (!lines_possible(g) || g.n_ring > 4096 || g.n_tof > 255) return LM_OK;
-  if (n < kMinEventsPerLine * nlines || n >= (1LL << 31) || nlines >= (1LL << 31)) return LM_OK;
+  if (n < kMinEventsPerLine * nlines || n >= (1LL << 31) || nlines > (long long)kGroupMaxBuckets) return LM_OK;
   int *key = nullptr;
-  unsigned *rank = nullptr, *cnt = nullptr, *off = nullptr;
-  LineRec *rec = nullptr;
+  unsigned *off = nullptr;
+  LineRec *rec = nullptr, *recu = nullptr;
   auto release = [&]() {  // release errors are not reported
     if (key) (void)hipFreeAsync(key, st);
-    if (rank) (void)hipFreeAsync(rank, st);
-    if (cnt) (void)hipFreeAsync(cnt, st);
     if (off) (void)hipFreeAsync(off, st);
     if (rec) (void)hipFreeAsync(rec, st);
+    if (recu) (void)hipFreeAsync(recu, st);
   };
   hipError_t e = hipMallocAsync((void **)&key, n * sizeof(int), st);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&rank, n * sizeof(unsigned), st);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&cnt, nlines * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&off, (nlines + 1) * sizeof(unsigned), st);
   if (e == hipSuccess) e = hipMallocAsync((void **)&rec, n * sizeof(LineRec), st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&recu, n * sizeof(LineRec), st);
   if (e == hipErrorOutOfMemory) {
     // no room for the sort: the per-event path needs no temporaries
     release();
     (void)hipGetLastError();
     return LM_OK;
   }
-  if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, nlines * sizeof(unsigned), st);
   const unsigned grid = (unsigned)((n + 255) / 256);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_keys, dim3(grid), dim3(256), 0, st, g, cyl, ev, v, n, key, rank, cnt);
+    hipLaunchKernelGGL(k_line_keys, dim3(grid), dim3(256), 0, st, g, cyl, ev, v, n, key, recu);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_offsets, dim3(1), dim3(1024), 0, st, cyl, cnt, nlines, off);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_line_place, dim3(grid), dim3(256), 0, st, g, cyl, ev, v, n, key, rank, off, rec);
-    e = hipGetLastError();
+    // events of no line (negative keys) are dropped from the records
+    static_assert(sizeof(LineRec) == sizeof(unsigned long long), "a record is one 64-bit payload");
+    const int rc = group_by_key((const unsigned *)key, (const unsigned long long *)recu, n, (unsigned)nlines, cyl,
+                                (unsigned long long *)rec, off, st);
+    if (rc == LM_ENOMEM) {
+      release();
+      lmh::clear_error();
+      return LM_OK;  // the per-event path
+    }
+    if (rc != LM_OK) {
+      release();
+      return rc;
+    }
   }
   const int na_max = std::max(g.n[0], g.n[1]);
   const int nchunk = (na_max + kLanes - 1) / kLanes;
