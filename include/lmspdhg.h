@@ -93,7 +93,7 @@ const char *lm_last_error(void);
  * that are out of range get out[e] = 0.  On a cylindrical scanner (as for
  * lm_back, decided on the device) a list of at least 64 events per
  * transaxial crystal pair and fewer than 2^31 events is projected by
- * transaxial line after a counting sort on the device: 16 more bytes per
+ * transaxial line after a counting sort on the device: 24 more bytes per
  * event of stream-ordered temporary memory (without room for it the events
  * are projected in their own order).  The result is the same up to float32
  * rounding in either order.  The call never synchronises the stream. */

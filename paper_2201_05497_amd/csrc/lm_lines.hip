@@ -749,6 +749,37 @@ __device__ __forceinline__ float fwd_event(const GeomDev &g, const float *__rest
   return __int_as_float(pk.q.w) * acc;
 }
 
+// Records of the sorted events of the lines (positions below off[nlines]):
+// {e, r1 | r2 << 12 | (k + kmax) << 24} in the line's orientation (crystal
+// c1 < c2: an event with c1 > c2 has its rings swapped and its TOF bin
+// mirrored), or kNoRec for an event that does not decode.  The line kernel
+// then reads its events in a row instead of gathering them through the
+// sorted order.
+constexpr unsigned kNoRec = ~0u;
+
+__global__ __launch_bounds__(256) void k_fwd_recs(GeomDev g, const int *cyl, const int16_t *__restrict__ ev,
+                                                  const unsigned *__restrict__ order, const unsigned *off,
+                                                  long long nlines, uint2 *__restrict__ rec) {
+  if (!*cyl) return;
+  const unsigned pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= off[nlines]) return;
+  const unsigned e = order[pos];
+  const int16_t *r = ev + 5 * (size_t)e;
+  int id1, id2, k;
+  unsigned rk = kNoRec;
+  if (decode_event(g, r, id1, id2, k)) {
+    int r1 = r[1], r2 = r[3];
+    if (r[0] > r[2]) {
+      const int t = r1;
+      r1 = r2;
+      r2 = t;
+      k = -k;
+    }
+    rk = (unsigned)r1 | ((unsigned)r2 << 12) | ((unsigned)(k + g.kmax) << 24);
+  }
+  rec[pos] = make_uint2(e, rk);
+}
+
 // Blocks b < 8 ceil(nlines / 8): the events of one line each, sorted
 // positions off[L] .. off[L + 1] with L = (b % 8) ceil(nlines / 8) + b / 8
 // (blocks are dealt to the XCDs round robin, so consecutive lines, which
@@ -758,8 +789,9 @@ __device__ __forceinline__ float fwd_event(const GeomDev &g, const float *__rest
 // unless *cyl is set.
 __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const int *cyl, const float *__restrict__ x,
                                                              const int16_t *__restrict__ ev, const unsigned *order,
-                                                             const unsigned *off, long long nlines, TofTab tt,
-                                                             const float4 *tab, float *__restrict__ out) {
+                                                             const uint2 *__restrict__ rec, const unsigned *off,
+                                                             long long nlines, TofTab tt, const float4 *tab,
+                                                             float *__restrict__ out) {
   extern __shared__ float4 sh4[];
   if (!*cyl) return;
   const int tid = threadIdx.x, grp = tid >> 3, gl = tid & 7;
@@ -816,22 +848,15 @@ __global__ __launch_bounds__(kFwdLineBlock) void k_fwd_lines(GeomDev g, const in
   __syncthreads();
   const double ihz = 1.0 / g.h[2];
   for (unsigned pos = e0 + grp; pos < e1; pos += kFwdLineGroups) {
-    const unsigned e = order[pos];
-    const int16_t *r = ev + 5 * (size_t)e;
-    int id1, id2, k;
+    const uint2 rr = rec[pos];
+    const unsigned e = rr.x;
     float val = 0.0f;
-    if (decode_event(g, r, id1, id2, k)) {
-      int r1 = r[1], r2 = r[3];
-      if (r[0] > r[2]) {  // the line's orientation: swap the ends, mirror the TOF bin
-        const int t = r1;
-        r1 = r2;
-        r2 = t;
-        k = -k;
-      }
+    if (rr.y != kNoRec) {
+      const int r1 = (int)(rr.y & 4095u), r2 = (int)((rr.y >> 12) & 4095u), k = (int)(rr.y >> 24) - g.kmax;
       const float z1f = g.det[3 * (g.n_cry * r1) + 2], z2f = g.det[3 * (g.n_cry * r2) + 2];
       const float *d1 = g.det + 3 * c1, *d2 = g.det + 3 * c2;
       if (dominant_axis(d2[0] - d1[0], d2[1] - d1[1], z2f - z1f) == 2) {
-        float acc = fwd_event(g, x, r, D, gl);
+        float acc = fwd_event(g, x, ev + 5 * (size_t)e, D, gl);
         val = group_sum<8>(acc);
       } else {
         const LineLor o = line_lor(g, q, z1f, z2f, k, D, ihz);
@@ -1022,25 +1047,45 @@ int build_tof_table(const GeomDev &g, TofTab &t, float4 **tab, hipStream_t st) {
 int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int16_t *ev, const unsigned *order,
                      const unsigned *off, long long n, float *out, hipStream_t st, bool &queued) {
   queued = false;
-  if (!lines_possible(g) || n == 0) return LM_OK;
+  // the records hold rings in 12 bits and the TOF bin in 8
+  if (!lines_possible(g) || n == 0 || g.n_ring > 4096 || g.n_tof > 255 || n >= (1LL << 32)) return LM_OK;
   int lds_max = 0;
   if (int rc = lds_per_block(lds_max)) return rc;
   if (fwd_sheet_bytes(g) > (size_t)lds_max) return LM_OK;
+  uint2 *rec = nullptr;
+  {
+    const hipError_t ea = hipMallocAsync((void **)&rec, (size_t)n * sizeof(uint2), st);
+    if (ea == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return LM_OK;  // the per-event walk in the sorted order
+    }
+    LM_TRY_HIP(ea);
+  }
+  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
+  hipLaunchKernelGGL(k_fwd_recs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, cyl, ev, order, off, nlines,
+                     rec);
+  if (const hipError_t ek = hipGetLastError(); ek != hipSuccess) {
+    (void)hipFreeAsync(rec, st);
+    LM_TRY_HIP(ek);
+  }
   TofTab tt{};
   float4 *tab = nullptr;
-  if (int rc = build_tof_table(g, tt, &tab, st)) return rc;
+  if (int rc = build_tof_table(g, tt, &tab, st)) {
+    (void)hipFreeAsync(rec, st);
+    return rc;
+  }
   size_t bytes = fwd_sheet_bytes(g) + (tab ? (size_t)tof_tab_size(tt) * sizeof(float4) : 0);
   if (bytes > (size_t)lds_max) {  // the sheet alone fits: erfc weights
     if (tab) (void)hipFreeAsync(tab, st);
     tab = nullptr;
     bytes = fwd_sheet_bytes(g);
   }
-  const long long nlines = (long long)g.n_cry * (g.n_cry - 1) / 2;
   const long long nb = 8 * ((nlines + 7) / 8) + kFwdTailBlocks;
-  hipLaunchKernelGGL(k_fwd_lines, dim3((unsigned)nb), dim3(kFwdLineBlock), bytes, st, g, cyl, x, ev, order, off,
+  hipLaunchKernelGGL(k_fwd_lines, dim3((unsigned)nb), dim3(kFwdLineBlock), bytes, st, g, cyl, x, ev, order, rec, off,
                      nlines, tt, tab, out);
   const hipError_t e = hipGetLastError();
-  if (tab) (void)hipFreeAsync(tab, st);  // a release error has no caller to go to
+  if (tab) (void)hipFreeAsync(tab, st);  // release errors have no caller to go to
+  (void)hipFreeAsync(rec, st);
   LM_TRY_HIP(e);
   queued = true;
   return LM_OK;
