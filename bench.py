@@ -124,9 +124,9 @@ PMC_TRAFFIC: dict = {
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     # one lm_fwd / lm_back call over the 5e8-event long frame: the counting
     # sort and the line kernels
-    "fwd": {"fetch_bytes": 105600000000, "write_bytes": 48800000000, "sources": "383a92795a17c4c7",
+    "fwd": {"fetch_bytes": 104600000000, "write_bytes": 52000000000, "sources": "cfd073d3f5ea28e3",
         "profile": "profiles/pass_3d_300x300x96_counters.txt"},
-    "back": {"fetch_bytes": 95400000000, "write_bytes": 118500000000, "sources": "383a92795a17c4c7",
+    "back": {"fetch_bytes": 95400000000, "write_bytes": 118500000000, "sources": "cfd073d3f5ea28e3",
         "profile": "profiles/pass_3d_300x300x96_counters.txt"},
 }
 
