@@ -114,6 +114,11 @@ int sort_events_by_line(const GeomDev &g, const int16_t *ev, long long n, unsign
 // otherwise.  x in the brick layout of g.
 int launch_fwd_lines(const GeomDev &g, const int *cyl, const float *x, const int16_t *ev, const unsigned *order,
                      const unsigned *off, long long n, float *out, hipStream_t st, bool &queued);
+// The tabulated TOF weights of a geometry with TOF (see TofTab): *tab is a
+// stream-ordered allocation of tof_tab_size(t) intervals that the caller
+// frees, or nullptr (no TOF, a table too large, or no memory for it: the
+// kernels then evaluate erfc).
+int build_tof_table(const GeomDev &g, TofTab &t, float4 **tab, hipStream_t st);
 // Plan-internal event records: int4 {id1, id2, k, s bits}.
 int launch_fwd_rec(const GeomDev &g, const float *x, const int4 *rec, long long n, float *out,
                    hipStream_t st);

@@ -210,39 +210,116 @@ __global__ __launch_bounds__(kScanB) void k_block_scan(const unsigned *in, long 
   if (i == n - 1) out[n] = (unsigned long long)boff[blockIdx.x] + s[t];
 }
 
+// A ray of phase 1 as the lanes of its event's group read it from LDS.
+struct TileRay {
+  int4 p;    // {m0, nplanes, a, I1}
+  int4 q;    // {I2, F1, V1, F2} (floats as bits)
+  float4 r;  // {V2, A, B, L}
+};
+
 // Phase 1: per event (8 lanes), the forward projection, the dual prox (the
 // cancellation-free form of k_data_update), and the event's segment
 // records.  Lane l takes the planes m = 8 c + l of the 8-plane chunks c the
 // ray visits, so the values of a chunk's 8 planes sit in the 8 lanes.
-template <int J8>
+// The double-precision set-up of the block's 32 rays runs once per ray, in
+// the first wavefront (one ray per lane), instead of in every lane of each
+// group; the other wavefronts wait for it at the barrier.  With TAB the
+// TOF weights come from the geometry's table (copied to LDS), otherwise
+// from erfc.
+template <int J8, bool TAB>
 __global__ __launch_bounds__(kBlock1) void k_tile_fwd(GeomDev g, TileGeom tg, int maxp, const float *__restrict__ x,
                                                       const int4 *__restrict__ rec, const float *__restrict__ S,
                                                       const float *__restrict__ mu, float *__restrict__ cdual,
                                                       long long n, const unsigned long long *__restrict__ eoff,
-                                                      TileRec *__restrict__ out) {
+                                                      TileRec *__restrict__ out, TofTab tt,
+                                                      const float4 *__restrict__ tab) {
+  constexpr int kEv = kBlock1 / kLanes1;  // events per block
+  __shared__ TileRay rays[kEv];
+  extern __shared__ float4 stab[];  // TAB: tof_tab_size(tt) intervals (dynamic LDS)
+  const long long e_first = (long long)blockIdx.x * kEv;
+  if (threadIdx.x < kEv) {
+    const long long e = e_first + threadIdx.x;
+    Ray r{};
+    if (e < n) {
+      const int4 rc = rec[e];
+      r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
+    }
+    TileRay t;
+    t.p = make_int4(r.m0, r.nplanes, r.a, r.I1);
+    t.q = make_int4(r.I2, __float_as_int(r.F1), __float_as_int(r.V1), __float_as_int(r.F2));
+    t.r = make_float4(r.V2, r.A, r.B, r.L);
+    rays[threadIdx.x] = t;
+  }
+  if constexpr (TAB) {
+    const int nt = tof_tab_size(tt);
+    for (int i = threadIdx.x; i < nt; i += kBlock1) stab[i] = tab[i];
+  }
+  __syncthreads();
   const int lane = threadIdx.x % kLanes1;
-  const long long e = (long long)blockIdx.x * (kBlock1 / kLanes1) + threadIdx.x / kLanes1;
+  const long long e = e_first + threadIdx.x / kLanes1;
   if (e >= n) return;
-  const int4 rc = rec[e];
+  Ray r{};
+  {
+    const TileRay t = rays[threadIdx.x / kLanes1];
+    r.m0 = t.p.x;
+    r.nplanes = t.p.y;
+    r.a = t.p.z;
+    r.I1 = t.p.w;
+    r.I2 = t.q.x;
+    r.F1 = __int_as_float(t.q.y);
+    r.V1 = __int_as_float(t.q.z);
+    r.F2 = __int_as_float(t.q.w);
+    r.V2 = t.r.x;
+    r.A = t.r.y;
+    r.B = t.r.z;
+    r.L = t.r.w;
+  }
+  const int b1 = (r.a == 0) ? 1 : 0, b2 = (r.a == 2) ? 1 : 2;
+  r.n1 = sel3(b1, g.n[0], g.n[1], g.n[2]);
+  r.n2 = sel3(b2, g.n[0], g.n[1], g.n[2]);
   const float Se = S[e];
-  const Ray r = setup_ray(g, rc.x, rc.y, rc.z, W_BIN, maxp);
+  const float s_e = __int_as_float(rec[e].w);
   const int off8 = r.m0 & (kTE - 1);
   float wj[J8];
   float acc = 0.0f;
+  {
+    const AxisTerm ta = axis_term(g.lay, r.a), t1 = axis_term(g.lay, b1), t2 = axis_term(g.lay, b2);
+    const TofTab tu = tof_tab_uniform(tt);
+    const float D = tof_bin_width(g);
+    // plane term of the lane's first plane m0 - off8 + lane, advanced by a
+    // chunk of 8 planes (two bricks) per step
+    int fa = axis_index(ta, r.m0 - off8 + lane);
+    const int fa_step = (kTE >> ta.s) * ta.bs;
+    // one sample's loads at a time: issuing every sample's gathers first
+    // (40 loads in flight, 99 VGPRs) lowered the occupancy and made the
+    // kernel slower (48.3 against 45.1 us per C2 update)
 #pragma unroll
-  for (int jj = 0; jj < J8; ++jj) {
-    const int j = lane + jj * kLanes1 - off8;
-    wj[jj] = 0.0f;
-    if (Se != 0.0f && j >= 0 && j < r.nplanes) {
-      const Sample s = sample_at(g, r, j, g.tof_on);
-      wj[jj] = s.w;
-      acc = fmaf(s.w, gather(g, x, r, s), acc);
+    for (int jj = 0; jj < J8; ++jj, fa += fa_step) {
+      const int j = lane + jj * kLanes1 - off8;
+      wj[jj] = 0.0f;
+      if (Se != 0.0f && j >= 0 && j < r.nplanes) {
+        const float u1 = fmaf((float)j, r.V1, r.F1), u2 = fmaf((float)j, r.V2, r.F2);
+        const float fl1 = floorf(u1), fl2 = floorf(u2);
+        // the loads first: the TOF weight's arithmetic runs while they are
+        // in flight; corners outside the image read as zero, the same
+        // values as gather()
+        const float v = gather_terms(x, t1, t2, r.n1, r.n2, fa, r.I1 + (int)fl1, r.I2 + (int)fl2, u1 - fl1,
+                                     u2 - fl2);
+        float w = 1.0f;
+        if (g.tof_on) {
+          const float vh = fmaf(-(float)j, r.B, r.A);
+          if constexpr (TAB) w = tof_weight_tab(tu, stab, vh);
+          else w = tof_weight(vh, vh - D, g.vclip, g.inv_norm);
+        }
+        wj[jj] = w;
+        acc = fmaf(w, v, acc);
+      }
     }
   }
   acc = group_sum<kLanes1>(acc);
   float cf = 0.0f;
   if (Se != 0.0f) {  // LOR misses the image: the prox leaves y unchanged
-    const float q = fmaf(r.L, acc, __int_as_float(rc.w));
+    const float q = fmaf(r.L, acc, s_e);
     const float c = cdual[e], me = mu[e];
     const float sq = Se * q;
     const float t = sq - c;
@@ -479,7 +556,7 @@ size_t tile_bytes_bound(const GeomDev &g, long long n, int nsub) {
   const long long nbin = (long long)nsub * tg.ntiles;
   const size_t kept = (size_t)(n * per_event) * sizeof(unsigned) + (size_t)(n + 1) * sizeof(unsigned long long) +
                       (size_t)(nbin + 1) * sizeof(long long) + (size_t)tg.ntiles * sizeof(int) +
-                      (size_t)(nmax * per_event) * sizeof(TileRec);
+                      (size_t)(nmax * per_event) * sizeof(TileRec) + (size_t)kTofTabMax * sizeof(float4);
   const size_t temporary = (size_t)nbin * sizeof(unsigned) + (size_t)n * sizeof(unsigned) +
                            (size_t)((n + kScanB - 1) / kScanB) * (sizeof(unsigned) + sizeof(long long) + 8);
   return kept + temporary;
@@ -588,6 +665,13 @@ int build_tiles(const GeomDev &g, const int4 *rec, const std::vector<int> &off, 
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e);
   for (void *q : tmp) (void)hipFreeAsync(q, st);
   for (void *q : {(void *)soff, (void *)eoff, (void *)seg, (void *)ord, (void *)recs}) owned.push_back(q);
+  // phase 1 reads the TOF weights from a table where the geometry has one
+  TofTab tt{};
+  float4 *tab = nullptr;
+  if (int rc = build_tof_table(g, tt, &tab, st)) return rc;
+  if (tab) owned.push_back(tab);
+  tp.tt = tt;
+  tp.tab = tab;
   tp.on = true;
   tp.tg = tg;
   tp.maxp = maxp;
@@ -605,10 +689,18 @@ int launch_tile_fwd(const GeomDev &g, const TilePlan &tp, const float *x, const 
                     const float *mu, float *cdual, long long o, long long n, hipStream_t st) {
   if (n == 0) return LM_OK;
   const int jneed = j8_for(tp.maxp);
+  const size_t tab_lds = tp.tab ? (size_t)tof_tab_size(tp.tt) * sizeof(float4) : 0;
 #define LM_TF(J_)                                                                                               \
   if (jneed <= J_) {                                                                                            \
-    hipLaunchKernelGGL((k_tile_fwd<J_>), dim3(blocks(n, kBlock1 / kLanes1)), dim3(kBlock1), 0, st, g, tp.tg,     \
-                       tp.maxp, x, rec + o, S + o, mu + o, cdual + o, n, tp.eoff + o, tp.rec);             \
+    if (tp.tab)                                                                                                 \
+      hipLaunchKernelGGL((k_tile_fwd<J_, true>), dim3(blocks(n, kBlock1 / kLanes1)), dim3(kBlock1), tab_lds, st, \
+                         g,                                                                                     \
+                         tp.tg, tp.maxp, x, rec + o, S + o, mu + o, cdual + o, n, tp.eoff + o, tp.rec, tp.tt,   \
+                         tp.tab);                                                                               \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_tile_fwd<J_, false>), dim3(blocks(n, kBlock1 / kLanes1)), dim3(kBlock1), 0, st, g,  \
+                         tp.tg, tp.maxp, x, rec + o, S + o, mu + o, cdual + o, n, tp.eoff + o, tp.rec, tp.tt,   \
+                         tp.tab);                                                                               \
     LM_TRY_HIP(hipGetLastError());                                                                              \
     return LM_OK;                                                                                               \
   }

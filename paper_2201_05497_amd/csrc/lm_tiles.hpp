@@ -46,6 +46,8 @@ struct TilePlan {
   unsigned *seg = nullptr;       // record numbers (relative to the subset's first) of every tile, by subset and tile
   int *order = nullptr;          // tiles by decreasing load (launch order of phase 2)
   TileRec *rec = nullptr;        // [rec_max] segments of the subset being updated
+  TofTab tt{};                   // layout of the tabulated TOF weights
+  float4 *tab = nullptr;         // the table (nullptr: phase 1 evaluates erfc)
 };
 
 bool tiles_supported(const GeomDev &g);
