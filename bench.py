@@ -116,7 +116,7 @@ KERNEL_SOURCES = {
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
     # the data update by image tile: phase 1 (k_tile_fwd) + phase 2 (k_tile_back)
-    "data_update": {"fetch_bytes": 222100000, "write_bytes": 70100000, "sources": "ad2010f8c9e6f27d",
+    "data_update": {"fetch_bytes": 231500000, "write_bytes": 80000000, "sources": "13ecc7c407b27647",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     "tv": {"fetch_bytes": 106400000, "write_bytes": 77000000, "sources": "5157d7dc3cd01a2c",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
@@ -134,7 +134,7 @@ PMC_TRAFFIC: dict = {
 # VALU wavefront instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU),
 # with the digest of the kernel's sources at the time.
 PMC_VALU: dict = {
-    "data_update": {"instr_per_launch": 46350000, "sources": "ad2010f8c9e6f27d",
+    "data_update": {"instr_per_launch": 40750000, "sources": "13ecc7c407b27647",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
 }
 
@@ -314,12 +314,14 @@ def epoch_leg(args, torch, P, lmsynth):
     torch.cuda.synchronize()
     if args.timing_every > 0:
         plan.timing(args.timing_every)
+    plan.set_tracing(args.trace)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         plan.epoch(x, seqs[k])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
+    plan.set_tracing(False)
     timing = plan.get_timing() if args.timing_every > 0 else None
     plan.timing(0)
     dtv = dtv_epochs(torch, P, lmsynth, plan, x, G, u)
@@ -863,6 +865,8 @@ def main() -> int:
                          "autograd, serving or long-frame legs")
     ap.add_argument("--timing-every", type=int, default=8,
                     help="bracket every k-th launch of each kernel class with HIP events (0: no per-kernel timing)")
+    ap.add_argument("--trace", action="store_true",
+                    help="roctx ranges per update in the timed epochs of the epoch leg (lm_plan_set_tracing)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain copy of known size (for scaling profiler HBM counters)")
     args = ap.parse_args()

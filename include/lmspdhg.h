@@ -329,6 +329,16 @@ enum {
 int lm_plan_timing(lm_plan *p, int every);
 int lm_plan_get_timing(lm_plan *p, double *ms, int64_t *launches);
 
+/* Tracing of lm_spdhg_epoch.  With on != 0 every later epoch call pushes a
+ * roctx range "lm_spdhg_epoch" for the call and, inside it, one range per
+ * update of Algorithm 2 ("data update, subset i" or "prior update") around
+ * the launches that update enqueues; the ranges are host-side (they mark
+ * when the launches were enqueued), so that a trace taken with rocprofv3
+ * --marker-trace --kernel-trace ties every kernel to its update.  on = 0
+ * (the default) turns tracing off; the iterates are the same either way.
+ * LM_EINVAL for a NULL plan. */
+int lm_plan_set_tracing(lm_plan *p, int on);
+
 /* Synchronises the plan's last stream, then frees its device memory
  * stream-ordered on that stream (hipFreeAsync: no device-wide wait).  That
  * stream (the one of the plan's last call) must still exist.  A plan is not

@@ -353,6 +353,10 @@ class Plan:
         launch of each kernel class (0 or False: off, True: every launch)."""
         _lib.check(_L.lm_plan_timing(self._handle(), int(every)), "lm_plan_timing")
 
+    def set_tracing(self, on: bool = True) -> None:
+        """roctx ranges per epoch() call and per update (lm_plan_set_tracing)."""
+        _lib.check(_L.lm_plan_set_tracing(self._handle(), int(bool(on))), "lm_plan_set_tracing")
+
     def get_timing(self):
         """{kernel: (total ms, timed launches)} since the last reset (synchronises)."""
         ms = (ctypes.c_double * len(self.KERNELS))()

@@ -56,6 +56,7 @@ SIGNATURES = {
     "lm_plan_get_state": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), _VP]),
     "lm_plan_set_state": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I64, _VP]),
     "lm_plan_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "lm_plan_set_tracing": (ctypes.c_int, [_VP, ctypes.c_int]),
     "lm_plan_get_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lm_plan_destroy": (ctypes.c_int, [_VP]),
     "lm_emtv": (ctypes.c_int, [_GP, _VP, _VP, _I64, _I32, _I32, _VP, ctypes.c_float, _I32, _VP, _VP]),

@@ -29,6 +29,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lm_blur.hpp"
 #include "lm_device.hpp"
 #include "lm_dtv.hpp"
@@ -107,7 +109,26 @@ struct lm_plan {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double t_ms[LM_K_COUNT] = {0};
   long long t_n[LM_K_COUNT] = {0};
+  bool trace = false;                              // roctx ranges per epoch call and update
 };
+
+namespace {
+
+// A roctx range from construction to destruction (when on), so that early
+// returns close it.
+struct TraceRange {
+  bool on;
+  TraceRange(bool on_, const char *name) : on(on_) {
+    if (on) roctxRangePushA(name);
+  }
+  ~TraceRange() {
+    if (on) roctxRangePop();
+  }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
+
+}  // namespace
 
 namespace {
 
@@ -576,6 +597,7 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
   for (int u = 0; u < n_updates; ++u)
     LM_REQUIRE(seq[u] >= 0 && seq[u] <= p->nsub, LM_EINVAL, "seq[%d] = %d outside [0, %d]", u, seq[u], p->nsub);
   if (n_updates == 0) return LM_OK;
+  const TraceRange epoch_range(p->trace, "lm_spdhg_epoch");
   hipStream_t st = lmh::as_stream(stream);
   p->last = st;
   const long long E = p->ne;
@@ -587,9 +609,15 @@ int lm_spdhg_epoch(lm_plan *p, float *x, const int32_t *seq, int32_t n_updates, 
         return r ? r : lmk::launch_primal(xi, p->T, p->zbar, E, st);
       }))
     return rc;
+  char range_name[48] = "prior update";
   for (int u = 0; u < n_updates; ++u) {
     const int i = seq[u];
     const bool fuse = u + 1 < n_updates;
+    if (p->trace) {
+      if (i < p->nsub) std::snprintf(range_name, sizeof range_name, "data update, subset %d", i);
+      else std::snprintf(range_name, sizeof range_name, "prior update");
+    }
+    const TraceRange update_range(p->trace, range_name);
     if (i < p->nsub) {
       const long long o = p->off[i], c = p->off[i + 1] - p->off[i];
       if (p->tiles.on && !p->blur.on) {
@@ -871,6 +899,13 @@ int lm_plan_set_state(lm_plan *p, const float *z, const float *zbar, const float
   LM_TRY_HIP(hipMemsetAsync(p->dz, 0, p->ne * sizeof(float), st));
   p->u = u;
   p->initialized = true;
+  return LM_OK;
+}
+
+int lm_plan_set_tracing(lm_plan *p, int on) {
+  lmh::clear_error();
+  LM_REQUIRE(p, LM_EINVAL, "NULL plan");
+  p->trace = on != 0;
   return LM_OK;
 }
 

@@ -120,6 +120,7 @@ def test_new_entry_points_check_arguments_first(lib):
     assert L.lm_plan_set_prior_image(None, P_, 0.1, None) == lib.LM_EINVAL
     assert L.lm_plan_set_event_factors(None, P_, None) == lib.LM_EINVAL
     assert L.lm_plan_set_resolution(None, f3, None) == lib.LM_EINVAL
+    assert L.lm_plan_set_tracing(None, 1) == lib.LM_EINVAL
 
 
 def test_noalloc_size_limit_host_only(lib):

@@ -401,6 +401,27 @@ def test_empty_subsets_match_oracle(P):
                  events=ev, s=s)
 
 
+def test_tracing_changes_nothing(P):
+    """lm_plan_set_tracing wraps each update in a host-side roctx range;
+    the iterates of a traced epoch are those of an untraced one (same plan
+    state, same sequence; the 2D plan's data updates use atomics, so the
+    comparison allows their last-bit differences)."""
+    p = problem_2d()
+    n = 28
+    seq = lmsynth.subset_sequence(11, 0, 2 * n, n)
+    xs = []
+    for on in (False, True, False):
+        Gg, plan = _plan(P, p, n, sens_2d(), 0.03)
+        x = torch.as_tensor(p.x0, device="cuda").clone()
+        plan.init(x)
+        plan.set_tracing(on)
+        plan.epoch(x, seq)
+        plan.epoch(x, seq)
+        xs.append(x.cpu().numpy())
+        plan.destroy()
+    assert img_err(xs[1], xs[0]) <= 1e-5 and img_err(xs[2], xs[0]) <= 1e-5
+
+
 def test_kernel_timing_sampling(P):
     """lm_plan_timing(p, k) brackets every k-th launch of each kernel class;
     timing changes nothing in the iterates."""
