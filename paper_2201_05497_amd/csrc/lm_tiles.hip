@@ -59,8 +59,10 @@ namespace {
 
 constexpr int kTE = 8;                 // tile edge, voxels
 constexpr int kTV = kTE * kTE * kTE;   // voxels per tile
-constexpr int kWaves2 = 8;             // wavefronts per phase-2 workgroup
+constexpr int kWaves2 = 4;             // wavefronts per phase-2 workgroup
 constexpr int kBlock2 = 64 * kWaves2;
+constexpr int kVoxPerThread = kTV / kBlock2;  // voxels of the tile per phase-2 thread
+static_assert(kBlock2 <= kTV && kTV % kBlock2 == 0, "phase-2 threads cover the tile's voxels evenly");
 constexpr int kLanes1 = 8;             // lanes per event in phase 1
 constexpr int kBlock1 = 256;
 constexpr int kMaxJ8 = 16;             // phase 1 caches up to 16 samples per lane
@@ -70,9 +72,11 @@ constexpr int kMaxJ8 = 16;             // phase 1 caches up to 16 samples per la
 // the 200x200x96 image (7500 tiles) with 4.5e4 events per subset (6 per
 // tile) a data update takes 115 us by tile (49 us phase 1, 66 us phase 2)
 // against 137 us per event (118 us, then 19 us for the z / zbar pass).
-// Workgroups of 8 wavefronts (16 LDS copies, 32 KB) run four to a CU and
-// hide each other's latency: 16 wavefronts took 92 us in phase 2, 4 took
-// 67 us.
+// Phase 2 runs workgroups of 4 wavefronts (8 LDS copies of the tile, 16
+// KB; each thread owns two of the tile's voxels): a wavefront's fixed work
+// (clearing its share of the copies, loading and finishing its voxels) is
+// shared by about 20 records on that image.  With 8 wavefronts phase 2
+// took 43.9 us per update, with 4 35.8 us, with 2 44.1 us.
 constexpr long long kMinEventsPerTile = 4;
 
 // Calls f(tile) for every tile that a corner of a sample of ray r on planes
@@ -412,6 +416,7 @@ __device__ __forceinline__ void seg_voxel(const SegLane &s, float fjp, int corne
 
 // Phase 2: one workgroup per tile; recs are the subset's records, seg the
 // record numbers of every tile, off the subset's per-tile ranges of seg.
+// The LDS copies are cleared with 16-byte stores.
 // Each wavefront takes records two at a time (one per half), unrolled by
 // two with alternating buffers so that the next records' loads are in
 // flight while the current ones are added.
@@ -422,29 +427,36 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
                                                        float *__restrict__ x, const float *__restrict__ T,
                                                        float *__restrict__ zbar, float *__restrict__ dz_out,
                                                        float inv_p, int fuse) {
-  __shared__ float acc[2 * kWaves2][kTV];
+  __shared__ __align__(16) float acc[2 * kWaves2][kTV];
   const int tile = order[blockIdx.x];
   const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, tz = tile / (tg.ntx * tg.nty);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const int jp = hl >> 2, corner = hl & 3;
   const float fjp = (float)jp;
-  // this thread's voxel of the tile (threads in the plan's brick order);
-  // its image values are loaded now and used at the end
+  // the thread's voxels v = threadIdx.x + kBlock2 q of the tile (threads in
+  // the plan's brick order); their image values are loaded now and used at
+  // the end
   const Layout &L = g.lay;
-  const int v = threadIdx.x;
-  const int b = (v >> 6) & 7, bi = tx * 2 + (b & 1), bj = ty * 2 + ((b >> 1) & 1), bk = tz * 2 + (b >> 2);
-  const bool mine_vox = v < kTV && bi < L.nbx && bj < L.nby && bk < L.nbz;
-  const long long gi = ((((long long)bk * L.nby + bj) * L.nbx + bi) << 6) | (v & 63);
-  float xv = 0.0f, zv = 0.0f, Tv = 0.0f;
-  if (mine_vox && !dz_out) {
-    zv = z[gi];
-    if (fuse) {
-      xv = x[gi];
-      Tv = T[gi];
+  bool mine_vox[kVoxPerThread];
+  long long gi[kVoxPerThread];
+  float xv[kVoxPerThread], zv[kVoxPerThread], Tv[kVoxPerThread];
+#pragma unroll
+  for (int q = 0; q < kVoxPerThread; ++q) {
+    const int v = threadIdx.x + kBlock2 * q;
+    const int b = (v >> 6) & 7, bi = tx * 2 + (b & 1), bj = ty * 2 + ((b >> 1) & 1), bk = tz * 2 + (b >> 2);
+    mine_vox[q] = bi < L.nbx && bj < L.nby && bk < L.nbz;
+    gi[q] = ((((long long)bk * L.nby + bj) * L.nbx + bi) << 6) | (v & 63);
+    xv[q] = zv[q] = Tv[q] = 0.0f;
+    if (mine_vox[q] && !dz_out) {
+      zv[q] = z[gi[q]];
+      if (fuse) {
+        xv[q] = x[gi[q]];
+        Tv[q] = T[gi[q]];
+      }
     }
   }
-  float *all = &acc[0][0];
-  for (int i = threadIdx.x; i < 2 * kWaves2 * kTV; i += kBlock2) all[i] = 0.0f;
+  float4 *all = reinterpret_cast<float4 *>(&acc[0][0]);
+  for (int i = threadIdx.x; i < 2 * kWaves2 * kTV / 4; i += kBlock2) all[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   float *mine = acc[2 * wv + half];
   const long long s0 = off[tile];
@@ -486,24 +498,29 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
     }
   }
   __syncthreads();
-  if (!mine_vox) return;
-  // voxel v of the brick-ordered tile: row-major position in the copies
-  const int lv = (b & 1) * 4 + (v & 3) + kTE * (((b >> 1) & 1) * 4 + ((v >> 2) & 3)) +
-                 kTE * kTE * ((b >> 2) * 4 + ((v >> 4) & 3));
-  float d = 0.0f;
 #pragma unroll
-  for (int c = 0; c < 2 * kWaves2; ++c) d += acc[c][lv];
-  if (dz_out) {
-    dz_out[gi] = d;
-    return;
+  for (int q = 0; q < kVoxPerThread; ++q) {
+    if (!mine_vox[q]) continue;
+    // voxel v of the brick-ordered tile: row-major position in the copies
+    const int v = threadIdx.x + kBlock2 * q;
+    const int b = (v >> 6) & 7;
+    const int lv = (b & 1) * 4 + (v & 3) + kTE * (((b >> 1) & 1) * 4 + ((v >> 2) & 3)) +
+                   kTE * kTE * ((b >> 2) * 4 + ((v >> 4) & 3));
+    float d = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 2 * kWaves2; ++c) d += acc[c][lv];
+    if (dz_out) {
+      dz_out[gi[q]] = d;
+      continue;
+    }
+    const float zn = zv[q] + d;
+    const float zb = fmaf(d, inv_p, zn);
+    z[gi[q]] = zn;
+    if (fuse)
+      x[gi[q]] = fmaxf(0.0f, fmaf(-Tv[q], zb, xv[q]));
+    else
+      zbar[gi[q]] = zb;
   }
-  const float zn = zv + d;
-  const float zb = fmaf(d, inv_p, zn);
-  z[gi] = zn;
-  if (fuse)
-    x[gi] = fmaxf(0.0f, fmaf(-Tv, zb, xv));
-  else
-    zbar[gi] = zb;
 }
 
 inline unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
