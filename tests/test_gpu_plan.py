@@ -499,20 +499,27 @@ def test_prior_updates_ragged_grids(P, shape):
     assert ex <= ITER_TOL and ez <= ITER_TOL and ew <= ITER_TOL
 
 
-@pytest.mark.parametrize("shape,dtv,fwhm", [((37, 29, 11), False, None), ((20, 33, 18), False, None),
-                                            ((37, 29, 11), True, None), ((20, 33, 18), True, None),
-                                            ((20, 33, 18), False, (1.5, 2.0, 1.2)),
-                                            ((37, 29, 11), False, (0.0, 0.0, 1.5))])
-def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm):
+@pytest.mark.parametrize("shape,dtv,fwhm,tof_mode", [((37, 29, 11), False, None, "on"), ((20, 33, 18), False, None, "on"),
+                                                     ((37, 29, 11), True, None, "on"), ((20, 33, 18), True, None, "on"),
+                                                     ((20, 33, 18), False, (1.5, 2.0, 1.2), "on"),
+                                                     ((37, 29, 11), False, (0.0, 0.0, 1.5), "on"),
+                                                     ((37, 29, 11), False, None, "off"),
+                                                     ((20, 33, 18), False, None, "wide")])
+def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm, tof_mode):
     """Mixed data and prior updates from a random state on ragged 3D grids,
     over two calls, against the oracle: data updates followed by prior
     updates and by data updates, prior updates in a row, and calls that end
     with either kind (the last update of a call materialises zbar instead
     of fusing the next primal step); with the TV prior, with the DTV prior
-    of a smooth structural image, and with a resolution model."""
+    of a smooth structural image, and with a resolution model.  Every case
+    takes the data update by image tile (5000 events per subset over at
+    most 60 tiles); its TOF weights come from the geometry's table ("on"),
+    are 1 ("off": no TOF), or come from erfc ("wide": a kernel truncated at
+    12 sigma, whose table would exceed its 1024 intervals)."""
     nx, ny, nz = shape
     sc = lmsynth.Scanner(96, 16, 120.0, 4.0)
-    tof = lmsynth.TOF(9, 24.0, 60.0, 3.0, True)
+    tof = {"on": lmsynth.TOF(9, 24.0, 60.0, 3.0, True), "off": lmsynth.TOF(9, 24.0, 60.0, 3.0, False),
+           "wide": lmsynth.TOF(9, 24.0, 60.0, 12.0, True)}[tof_mode]
     img = lmsynth.ImageGeom((nx, ny, nz), (3.0, 2.5, 3.5))
     p = lmsynth.simulate_3d(lmsynth.Problem("ragged", sc, img, tof, 4, 1, 0.03), n_prompts=20000, seed=78,
                             workers=1)
@@ -552,7 +559,8 @@ def test_mixed_updates_ragged_grids(P, shape, dtv, fwhm):
         ec = img_err(state["c"].cpu().numpy(), 1.0 - st.y)
         wg = state["w"].cpu().numpy().astype(np.float64)
         ew = float(np.linalg.norm(wg - st.w) / np.linalg.norm(st.w))
-        report(f"mixed updates {shape} dtv={dtv} fwhm={fwhm} call {k}", x_err=ex, z_err=ez, zbar_err=ezb, c_err=ec, w_l2=ew)
+        report(f"mixed updates {shape} dtv={dtv} fwhm={fwhm} tof={tof_mode} call {k}", x_err=ex, z_err=ez,
+               zbar_err=ezb, c_err=ec, w_l2=ew)
         assert max(ex, ez, ezb, ec, ew) <= ITER_TOL
 
 
