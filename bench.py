@@ -116,7 +116,7 @@ KERNEL_SOURCES = {
 # kernel's sources at the time.  The summaries are under profiles/.
 PMC_TRAFFIC: dict = {
     # the data update by image tile: phase 1 (k_tile_fwd) + phase 2 (k_tile_back)
-    "data_update": {"fetch_bytes": 231400000, "write_bytes": 80000000, "sources": "9be3f7ceb53dea62",
+    "data_update": {"fetch_bytes": 231500000, "write_bytes": 80000000, "sources": "96219cb1c080b05d",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
     "tv": {"fetch_bytes": 106400000, "write_bytes": 77000000, "sources": "5157d7dc3cd01a2c",
         "profile": "profiles/epoch_3d_200x200x96_hbm_traffic.txt"},
@@ -134,7 +134,7 @@ PMC_TRAFFIC: dict = {
 # VALU wavefront instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU),
 # with the digest of the kernel's sources at the time.
 PMC_VALU: dict = {
-    "data_update": {"instr_per_launch": 34890000, "sources": "9be3f7ceb53dea62",
+    "data_update": {"instr_per_launch": 33050000, "sources": "96219cb1c080b05d",
         "profile": "profiles/epoch_3d_200x200x96_l2_atomics_valu.txt"},
 }
 

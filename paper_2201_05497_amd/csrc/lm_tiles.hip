@@ -400,18 +400,44 @@ __device__ __forceinline__ SegLane load_seg(const TileRec *__restrict__ recs, un
   return s;
 }
 
+// What a phase-2 lane needs of its bilinear corner, fixed for the kernel:
+// the corner's offset from corner 0 in the tile's row-major index for each
+// dominant axis a of a record (minus the bias 128 of the index stored in
+// meta), the corner's weight as (b1 + s1 f1) (b2 + s2 f2), which is f or
+// 1 - f along each axis, and the corner's bit of the mask in meta.
+struct CornerLane {
+  int off0, off1, off2;
+  float s1, b1, s2, b2;
+  unsigned bit;
+};
+
+__device__ __forceinline__ CornerLane corner_lane(int corner) {
+  CornerLane c;
+  // strides of the two other axes in the tile's index (x fastest): a = 0
+  // (y, z), a = 1 (x, z), a = 2 (x, y)
+  const int c1 = corner & 1, c2 = (corner >> 1) & 1;
+  c.off0 = c1 * kTE + c2 * kTE * kTE - 128;
+  c.off1 = c1 * 1 + c2 * kTE * kTE - 128;
+  c.off2 = c1 * 1 + c2 * kTE - 128;
+  c.s1 = c1 ? 1.0f : -1.0f;
+  c.b1 = c1 ? 0.0f : 1.0f;
+  c.s2 = c2 ? 1.0f : -1.0f;
+  c.b2 = c2 ? 0.0f : 1.0f;
+  c.bit = 1u << (10 + corner);
+  return c;
+}
+
 // The voxel of lane (plane jp, corner) for record s: its tile-local
 // row-major index (li + 8 lj + 64 lk) and value, or add = 0.  The sample's
 // coordinates are computed as phase 1 computed them for its corner mask.
-__device__ __forceinline__ void seg_voxel(const SegLane &s, float fjp, int corner, float &add, int &at) {
+__device__ __forceinline__ void seg_voxel(const SegLane &s, float fjp, const CornerLane &cl, float &add, int &at) {
   const unsigned mt = s.meta;
-  const int a = (int)(mt >> 14);
-  const int d1 = a == 0 ? kTE : 1, d2 = a == 2 ? kTE : kTE * kTE;
-  at = (int)(mt & 1023u) - 128 + ((corner & 1) ? d1 : 0) + ((corner & 2) ? d2 : 0);
+  const unsigned a = mt >> 14;
+  at = (int)(mt & 1023u) + (a == 0 ? cl.off0 : (a == 1 ? cl.off1 : cl.off2));
   const float u1 = fmaf(fjp, s.h.y, s.h.x), u2 = fmaf(fjp, s.h.w, s.h.z);
   const float f1 = u1 - floorf(u1), f2 = u2 - floorf(u2);
-  const float wc = ((corner & 1) ? f1 : 1.0f - f1) * ((corner & 2) ? f2 : 1.0f - f2);
-  add = ((mt >> (10 + corner)) & 1u) ? s.v * wc : 0.0f;
+  const float wc = fmaf(cl.s1, f1, cl.b1) * fmaf(cl.s2, f2, cl.b2);
+  add = (mt & cl.bit) ? s.v * wc : 0.0f;
 }
 
 // Phase 2: one workgroup per tile; recs are the subset's records, seg the
@@ -431,7 +457,8 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
   const int tile = order[blockIdx.x];
   const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, tz = tile / (tg.ntx * tg.nty);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
-  const int jp = hl >> 2, corner = hl & 3;
+  const int jp = hl >> 2;
+  const CornerLane cl = corner_lane(hl & 3);
   const float fjp = (float)jp;
   // the thread's voxels v = threadIdx.x + kBlock2 q of the tile (threads in
   // the plan's brick order); their image values are loaded now and used at
@@ -478,7 +505,7 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
       const unsigned iD = idx(k + 3 * kStep);
       float add;
       int at;
-      seg_voxel(A, fjp, corner, add, at);
+      seg_voxel(A, fjp, cl, add, at);
       // the 32 lanes of a record touch distinct voxels of their own copy; a
       // lane may read a word another lane of the wavefront wrote before,
       // which the wavefront's in-order LDS operations deliver once the
@@ -489,7 +516,7 @@ __global__ __launch_bounds__(kBlock2) void k_tile_back(GeomDev g, TileGeom tg, c
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       A = load_seg(recs, iC, jp);
       iC = idx(k + 4 * kStep);
-      seg_voxel(B, fjp, corner, add, at);
+      seg_voxel(B, fjp, cl, add, at);
       if (k + kStep < cnt && add != 0.0f) mine[at] += add;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
